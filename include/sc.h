@@ -1,0 +1,174 @@
+/*
+ * sc.h -- C ABI of the MI355X (gfx950) sparse-coding hot path for
+ * post-training 3DGS compression ("Smaller and Faster 3DGS via Post-Training
+ * Dictionary Learning").
+ *
+ * The paper compresses each Gaussian's 45 view-dependent SH coefficients
+ * (the 48 SH values minus the 3 DC terms, Sec. 2.2) into a sparse code over a
+ * shared dictionary D of unit-norm atoms (Eq. (1)), found by Orthogonal
+ * Matching Pursuit that stops at sparsity k and/or residual tolerance eps
+ * (Sec. 2.1), and renders radiance directly from the codes (Sec. 2.2,
+ * Eq. (2)-(3)).  This library exposes that path:
+ *
+ *   sc_gram_precompute   dictionary set-up: checks, layouts, Gram matrix
+ *   sc_omp_encode        OMP of N signals (Batch-OMP on the GPU)
+ *   sc_sh_eval_sparse    radiance straight from (index, coefficient) codes
+ * and three additions around it: a learned support proposer (sc_proposer_*,
+ * sc_omp_encode_learned), a BF16/FP32/FP64 precision policy (flags of
+ * sc_omp_encode) and a batched persistent launch over many dictionaries
+ * (sc_omp_encode_batched).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller; the
+ *    library never frees it.  Handles own their own device memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    stream-ordered and asynchronous unless its comment says it synchronises.
+ *  - Return value: SC_OK (0) or a negative SC_E* code.  Argument errors are
+ *    detected on the host before any device work, so the outputs are then
+ *    untouched.  SC_EDEVICE means a HIP call failed; sc_last_error() gives
+ *    the HIP message.
+ *  - Layouts (row-major, 0-based):
+ *      D     K x d float32, atom-major: the paper's d x K matrix stored column
+ *            by column, each atom's d values contiguous.
+ *      X     N x d float32, one Gaussian per row, channel-major
+ *            [R_1..R_15, G_1..G_15, B_1..B_15] for d = 45.
+ *      idx   N x k int32, selected atoms in selection order, -1 padded.
+ *      coef  N x k float32, the least-squares coefficients, 0 padded.
+ *      count N int32, number of atoms used; -1 for a signal with a
+ *            non-finite entry (a per-signal status, not a call failure).
+ *      resid N float32, explicit ||x - D_I coef||_2 (NaN when count = -1).
+ *  - Limits: 1 <= d <= 64, 1 <= K <= 1024, 1 <= k <= min(K, d, 32).
+ */
+#ifndef SC_H
+#define SC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define SC_OK          0
+#define SC_EINVAL     -1   /* null pointer, bad size or range, unknown flag      */
+#define SC_ENORM      -2   /* an atom with | ||a_j|| - 1 | > 1e-4 (Eq. (1))       */
+#define SC_ENONFINITE -3   /* NaN/Inf in the dictionary or the proposer weights  */
+#define SC_EDEVICE    -4   /* a HIP runtime call or kernel launch failed         */
+#define SC_ENOMEM     -5   /* device allocation failed, or workspace too small   */
+#define SC_ENODEV     -6   /* no usable gfx950 device                            */
+
+/* ---- flags ---- */
+#define SC_EPS_RELATIVE  0x1  /* stop when ||r|| <= eps * ||x|| instead of eps     */
+#define SC_PREC_BF16     0x2  /* correlations on BF16 MFMA (FP32 otherwise)        */
+#define SC_NO_FP64_REFIT 0x4  /* never refit ill-conditioned supports in FP64      */
+#define SC_NORMALIZE     0x8  /* sc_gram_precompute: scale atoms to unit norm
+                                 instead of rejecting them                         */
+
+/* ---- radiance direction modes ---- */
+#define SC_DIRS_PER_SIGNAL 0  /* dirs is N x 3, rgb is N x 3                      */
+#define SC_DIRS_SHARED     1  /* dirs is M x 3 for every signal, rgb N x M x 3    */
+
+typedef struct sc_dict_s *sc_dict;
+typedef struct sc_proposer_s *sc_proposer;
+
+/* Human-readable text of an error code (static storage). */
+const char *sc_strerror(int code);
+/* Message of the last SC_EDEVICE failure on this thread (static storage). */
+const char *sc_last_error(void);
+
+/*
+ * sc_gram_precompute -- set up a dictionary D for encoding and rendering.
+ *
+ * Sec. 2.1 (Eq. (1)) requires unit-norm atoms; Batch-OMP precomputes the
+ * Gram matrix G = D^T D (K x K) once per dictionary.  The handle keeps, in
+ * device memory it owns: a copy of D (FP32), D feature-major and padded for
+ * the correlation stage, D in BF16 for MFMA, and G in FP32.
+ *
+ *   D      device, K x d float32 atom-major (caller-owned, read only here)
+ *   d, K   1 <= d <= 64, 1 <= K <= 1024
+ *   flags  0 or SC_NORMALIZE
+ *   out    receives the new handle (set only on success)
+ *
+ * Checks every atom (finite, unit norm within 1e-4 unless SC_NORMALIZE); this
+ * reads a status word back, so the call SYNCHRONISES with `stream`.
+ * Errors: SC_EINVAL, SC_ENONFINITE, SC_ENORM, SC_ENOMEM, SC_EDEVICE, SC_ENODEV.
+ */
+int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc_dict *out);
+
+/* Release a dictionary handle (waits for the device).  NULL is accepted. */
+int sc_dict_destroy(sc_dict h);
+
+/* Dimensions of a dictionary handle. */
+int sc_dict_dims(sc_dict h, int *d, int *K);
+
+/* Copy the handle's FP32 Gram matrix G = D^T D into G_out (device, K x K
+ * row-major, caller-owned).  Stream-ordered.  For inspection and tests. */
+int sc_dict_gram(sc_dict h, float *G_out, void *stream);
+
+/*
+ * sc_omp_encode -- sparse-code N signals with OMP (Sec. 2.1).
+ *
+ * Greedy selection of the atom with the largest |correlation| to the
+ * residual (ties to the lowest index, selected atoms excluded), least-squares
+ * coefficients on the selected atoms, stop before a selection when the
+ * residual norm is <= eps (or eps*||x|| with SC_EPS_RELATIVE) or k atoms are
+ * in use.  eps = 0 means "k atoms".  The GPU runs Batch-OMP: correlations
+ * alpha0 = D^T x once, then per step an incremental Cholesky row and a
+ * Gram-column update of the correlations, and finally a refit of the
+ * coefficients from D_I^T x.
+ *
+ * Precision (flags): FP32 throughout by default.  SC_PREC_BF16 computes the
+ * correlations on BF16 MFMA with FP32 accumulation (residual form: the
+ * correlations of the FP32 residual are recomputed every step) while the
+ * Cholesky factor, the stop test and the refit stay FP32.  Supports whose
+ * Cholesky condition estimate (max l_ii / min l_ii)^2 exceeds 1e3 are refit
+ * in FP64 unless SC_NO_FP64_REFIT.
+ *
+ *   X      device N x d float32          idx   device N x k int32 (out)
+ *   N      >= 0 (0: no device work, the  coef  device N x k float32 (out)
+ *          arrays may then be NULL)
+ *   k      1 <= k <= min(K, d, 32)       count device N int32 (out)
+ *   eps    >= 0, finite                  resid device N float32 (out, may be NULL)
+ * Errors: SC_EINVAL, SC_EDEVICE.
+ */
+int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, int32_t *idx,
+                  float *coef, int32_t *count, float *resid, void *stream);
+
+/*
+ * sc_omp_stats -- counters accumulated by the encoders of this handle since
+ * the last reset: stats[0] = signals encoded, stats[1] = total atoms
+ * selected, stats[2] = supports refit in FP64, stats[3] = signals sent to the
+ * full-OMP fallback by sc_omp_encode_learned.  Synchronises with `stream`
+ * when reading; reset = 1 clears them afterwards.
+ */
+int sc_omp_stats(sc_dict h, int64_t stats[4], int reset, void *stream);
+
+/*
+ * sc_sh_eval_sparse -- view-dependent radiance from sparse codes (Sec. 2.2).
+ *
+ * For each signal and view direction w:
+ *   rgb_c(w) = sum_{t < count} coef_t * sum_{j=1..nb} D[idx_t][c*nb + j] * Y_j(w)
+ * with Y_j the real SH basis of degree 1..L (Condon-Shortley phase, m = -l..l
+ * within each band l), nb = (L+1)^2 - 1 and d = 3 nb, so d in {9, 24, 45}.
+ * Only the linear view-dependent part is returned (no DC term, offset or
+ * clamp).  Signals with count < 0 give NaN.  Indices outside [0, K) are
+ * skipped.
+ *
+ *   idx, coef   device N x k codes (as written by sc_omp_encode)
+ *   count       device N int32
+ *   dirs        device float32 unit vectors: N x 3 (SC_DIRS_PER_SIGNAL, M = N)
+ *               or M x 3 (SC_DIRS_SHARED)
+ *   rgb         device float32 out: N x 3 or N x M x 3
+ * Errors: SC_EINVAL, SC_EDEVICE.
+ */
+int sc_sh_eval_sparse(sc_dict h, const int32_t *idx, const float *coef, const int32_t *count,
+                      int64_t N, int k, const float *dirs, int64_t M, int dir_mode, float *rgb,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SC_H */

@@ -97,6 +97,7 @@ typedef struct {
     int32_t *count;
     double *resid;
     double *margin;       /* optional: min over steps of (|c|_(1)-|c|_(2))/||r|| */
+    double *rpath;        /* optional N x (k+1): ||r|| after 0..count atoms, NaN after */
     int64_t lo, hi;
 } omp_job;
 
@@ -115,6 +116,9 @@ static void omp_one(const omp_job *J, int64_t s, double *ws, unsigned char *used
         x[i] = (double)J->X[s * d + i];
         if (!isfinite(x[i])) finite = 0;
     }
+    double *path = J->rpath ? J->rpath + s * (k + 1) : NULL;
+    if (path)
+        for (int t = 0; t <= k; ++t) path[t] = NAN;
     if (!finite) {
         J->count[s] = -1;
         J->resid[s] = NAN;
@@ -136,6 +140,7 @@ static void omp_one(const omp_job *J, int64_t s, double *ws, unsigned char *used
         double rn = 0.0;
         for (int i = 0; i < d; ++i) rn += r[i] * r[i];
         rn = sqrt(rn);
+        if (path) path[n] = rn;
         if (n >= k || rn <= eps_abs) break;
         int best = -1;
         double bv = -1.0, sv = 0.0;
@@ -202,11 +207,12 @@ static void *omp_worker(void *arg)
  * listed atoms only), NULL for the whole dictionary.
  * Outputs: idx N x k (selection order, -1 padded), coef N x k (0 padded),
  * count N, resid N (explicit ||x - D_I gamma||), margin N (optional, may be
- * NULL).  Returns 0, or -1 on bad arguments.
+ * NULL), rpath N x (k+1) (optional: the residual norm before each selection
+ * and at the end, NaN past the end).  Returns 0, or -1 on bad arguments.
  */
 int orc_omp(const float *D_atoms, int d, int K, const float *X, int64_t N, int k, double eps,
             int relative, const int32_t *cand, int n_cand, int32_t *idx, double *coef,
-            int32_t *count, double *resid, double *margin, int nthreads)
+            int32_t *count, double *resid, double *margin, double *rpath, int nthreads)
 {
     if (d <= 0 || K <= 0 || k <= 0 || k > d || N < 0 || !(eps >= 0.0)) return -1;
     if (cand && n_cand <= 0) return -1;
@@ -218,7 +224,7 @@ int orc_omp(const float *D_atoms, int d, int K, const float *X, int64_t N, int k
     omp_job *jobs = (omp_job *)malloc(sizeof(omp_job) * nthreads);
     for (int t = 0; t < nthreads; ++t) {
         omp_job J = {Dd, d, K, k, eps, relative, X, cand, n_cand, idx, coef, count, resid, margin,
-                     N * t / nthreads, N * (t + 1) / nthreads};
+                     rpath, N * t / nthreads, N * (t + 1) / nthreads};
         jobs[t] = J;
         pthread_create(&th[t], NULL, omp_worker, &jobs[t]);
     }

@@ -1,0 +1,58 @@
+// Wavefront-level primitives for gfx950 (64-lane waves).
+//
+// Reductions use DPP row operations inside each 16-lane row and read the four
+// row results with v_readlane, so the result is wave-uniform.  Every caller
+// must run them with all 64 lanes active.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sc {
+
+constexpr int kWave = 64;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror
+#define SC_DPP_QP1032 0xB1
+#define SC_DPP_QP2301 0x4E
+#define SC_DPP_HMIRROR 0x141
+#define SC_DPP_MIRROR 0x140
+
+// Max over the wave of non-NaN inputs (callers pass finite values).
+__device__ __forceinline__ float wave_max(float v) {
+    v = fmaxf(v, dpp_f<SC_DPP_QP1032>(v));
+    v = fmaxf(v, dpp_f<SC_DPP_QP2301>(v));
+    v = fmaxf(v, dpp_f<SC_DPP_HMIRROR>(v));
+    v = fmaxf(v, dpp_f<SC_DPP_MIRROR>(v));
+    return fmaxf(fmaxf(readlane_f(v, 0), readlane_f(v, 16)), fmaxf(readlane_f(v, 32), readlane_f(v, 48)));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_f<SC_DPP_QP1032>(v);
+    v += dpp_f<SC_DPP_QP2301>(v);
+    v += dpp_f<SC_DPP_HMIRROR>(v);
+    v += dpp_f<SC_DPP_MIRROR>(v);
+    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+    // FP64 reduction through 32-bit halves (DPP moves 32 bits)
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace sc

@@ -1,0 +1,179 @@
+"""GPU parity of the FP32 Batch-OMP encoder (sc_omp_encode) against the FP64
+oracle, through the C ABI."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_30396_amd import inputs as I
+from paper_2605_30396_amd import sc
+from parity import compare_codes, oracle_run
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def encode(D, X, k, eps, flags=0):
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    Xg = torch.from_numpy(np.ascontiguousarray(X)).to(DEV)
+    idx, coef, count, resid = sc.omp_encode(h, Xg, k, eps, flags)
+    torch.cuda.synchronize()
+    out = dict(idx=idx.cpu().numpy(), coef=coef.cpu().numpy(), count=count.cpu().numpy(),
+               resid=resid.cpu().numpy())
+    stats = sc.omp_stats(h)
+    h.destroy()
+    return out, stats
+
+
+def test_gram_matches_definition():
+    D = I.random_dictionary(I.rng_for(70), 300)
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    G = h.gram().cpu().numpy().astype(np.float64)
+    ref = D.astype(np.float64) @ D.astype(np.float64).T
+    assert np.abs(G - ref).max() <= 2 ** -24 * 2
+    h.destroy()
+
+
+def test_dictionary_checks():
+    D = I.random_dictionary(I.rng_for(71), 64)
+    bad = D.copy()
+    bad[5] *= 1.01
+    with pytest.raises(sc.ScError) as e:
+        sc.gram_precompute(torch.from_numpy(bad).to(DEV))
+    assert e.value.code == sc.SC_ENORM
+    nan = D.copy()
+    nan[3, 2] = np.nan
+    with pytest.raises(sc.ScError) as e:
+        sc.gram_precompute(torch.from_numpy(nan).to(DEV))
+    assert e.value.code == sc.SC_ENONFINITE
+    h = sc.gram_precompute(torch.from_numpy(bad * 3).to(DEV), flags=sc.NORMALIZE)
+    X = I.sparse_signals(I.rng_for(72), D, 64, 3)[0]
+    g, _ = encode(D, X, 4, 0.0)
+    out = sc.omp_encode(h, torch.from_numpy(X).to(DEV), 4)
+    np.testing.assert_array_equal(out[0].cpu().numpy(), g["idx"])  # normalised atoms = D
+    h.destroy()
+
+
+def test_argument_errors_with_handle():
+    D = I.random_dictionary(I.rng_for(73), 64)
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    X = torch.zeros((8, 45), device=DEV)
+    lib = sc.load()
+    for k in (0, 46, 65):
+        with pytest.raises(sc.ScError):
+            sc.omp_encode(h, X, k)
+    for eps in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(sc.ScError):
+            sc.omp_encode(h, X, 4, eps)
+    with pytest.raises(sc.ScError):
+        sc.omp_encode(h, X, 4, 0.0, flags=0x100)
+    # N = 0 is a no-op
+    idx, coef, count, resid = sc.omp_encode(h, torch.zeros((0, 45), device=DEV), 4)
+    assert idx.shape == (0, 4)
+    h.destroy()
+
+
+@pytest.mark.parametrize("N", [1, 16, 4096 + 37])
+def test_plain_small_workload(N):
+    """Gaussian K=64 dictionary, exactly 4-sparse signals + 1e-3 noise, k=4,
+    eps=0 -- several 16-signal tiles and a ragged tail."""
+    w = I.workload_plain_small(N=N)
+    g, stats = encode(w["D"], w["X"], 4, 0.0)
+    r = compare_codes(w["D"], w["X"], 4, 0.0, g, min_sep_frac=0.5 if N > 16 else 0.0)
+    assert stats["signals"] == N and stats["atoms"] == int(g["count"].sum())
+    print(r)
+
+
+def test_sh_like_workload_sample():
+    """SH-like signals with the oracle-learned K=256 dictionary, k=8,
+    eps=1e-3 (k binds), first 20k signals."""
+    D = np.load(os.path.join(GOLD, "sh_like_dict_K256.npy"))
+    X = I.sh_like_signals(I.rng_for(2), 20_000)
+    g, _ = encode(D, X, 8, 1e-3)
+    r = compare_codes(D, X, 8, 1e-3, g, min_sep_frac=0.3)
+    print(r)
+
+
+@pytest.mark.parametrize("K,k,eps,s", [(512, 12, 0.0, 4), (512, 12, 1e-2, 4), (128, 16, 0.0, 8),
+                                       (256, 8, 1e-2, 4), (90, 12, 0.0, 6), (1000, 8, 0.0, 4),
+                                       (640, 4, 0.0, 3), (48, 32, 0.0, 8)])
+def test_dictionary_and_sparsity_shapes(K, k, eps, s):
+    rng = I.rng_for(1000 + K + k)
+    D = I.random_dictionary(rng, K)
+    X, _, _ = I.sparse_signals(rng, D, 2000 + 5, s, 1e-3)
+    g, _ = encode(D, X, k, eps)
+    r = compare_codes(D, X, k, eps, g, min_sep_frac=0.3)
+    print(K, k, eps, r)
+
+
+def test_relative_tolerance_and_edge_signals():
+    rng = I.rng_for(74)
+    D = I.random_dictionary(rng, 256)
+    X, _, _ = I.sparse_signals(rng, D, 1000, 4, 1e-3)
+    X[0] = 0
+    X[1, 7] = np.nan
+    X[2, 0] = np.inf
+    X[3] *= np.float32(1e-3)
+    g, _ = encode(D, X, 12, 0.05, sc.EPS_RELATIVE)
+    assert g["count"][0] == 0 and g["resid"][0] == 0
+    assert g["count"][1] == -1 and g["count"][2] == -1 and np.isnan(g["resid"][1])
+    assert np.all(g["idx"][1] == -1)
+    compare_codes(D, X, 12, 0.05, g, relative=True, min_sep_frac=0.3)
+    ge, _ = encode(D, X, 12, 0.02)      # absolute: the tiny signal takes no atom
+    assert ge["count"][3] == 0
+
+
+def test_orthonormal_ties_and_hard_thresholding():
+    d = 45
+    D = np.eye(d, dtype=np.float32)
+    X = np.zeros((4, d), np.float32)
+    X[0, [3, 7, 9]] = [1.0, -1.0, 1.0]          # exact ties: lowest index first
+    X[1, [44, 0]] = [0.5, -0.5]
+    X[2] = np.arange(d, dtype=np.float32) / 10
+    X[3, 20] = 2.0
+    g, _ = encode(D, X, 5, 0.0)
+    ref = oracle.omp(D, X, 5)
+    np.testing.assert_array_equal(g["idx"], ref["idx"])
+    np.testing.assert_array_equal(g["count"], ref["count"])
+    np.testing.assert_allclose(g["coef"], ref["coef"], atol=1e-6)
+
+
+def test_ill_conditioned_support_refit_in_fp64():
+    a2 = np.array([1.0, 1e-3, 0.0]) / np.sqrt(1 + 1e-6)
+    D = np.array([[1, 0, 0], a2, [0, 0, 1]], np.float32)
+    X = np.array([[0, 1, 0]], np.float32)
+    ref = oracle.omp(D, X, 2)
+    g, stats = encode(D, X, 2, 0.0)
+    np.testing.assert_array_equal(g["idx"], ref["idx"])
+    assert stats["fp64_refits"] == 1
+    err = np.linalg.norm(g["coef"][0] - ref["coef"][0]) / np.linalg.norm(ref["coef"][0])
+    assert err <= 1e-4, err
+    g2, stats2 = encode(D, X, 2, 0.0, sc.NO_FP64_REFIT)
+    assert stats2["fp64_refits"] == 0
+
+
+def test_deterministic():
+    w = I.workload_plain_small(N=3000)
+    a, _ = encode(w["D"], w["X"], 4, 0.0)
+    b, _ = encode(w["D"], w["X"], 4, 0.0)
+    for key in a:
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+@pytest.mark.slow
+def test_full_size_sampled_learned_shape():
+    """The 6M-signal, K=512, k=12, eps=1e-2 workload at full size: every
+    signal encoded on the GPU, 3000 sampled signals checked by the oracle."""
+    D = I.learned_dictionary()
+    X = I.learned_eval_signals(D)
+    g, stats = encode(D, X, 12, 1e-2)
+    assert stats["signals"] == len(X)
+    rs = np.random.Generator(np.random.PCG64(9)).choice(len(X), 3000, replace=False)
+    sub = {k: v[rs] for k, v in g.items()}
+    r = compare_codes(D, X[rs], 12, 1e-2, sub, min_sep_frac=0.5)
+    assert np.all(g["count"] >= 1) and np.all(g["count"] <= 12)
+    print(r, "mean atoms", g["count"].mean())
