@@ -137,6 +137,19 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
                   float *coef, int32_t *count, float *resid, void *stream);
 
 /*
+ * Tuning of a dictionary handle (chosen by the autotuner; results do not
+ * depend on it beyond FP32 rounding order):
+ *   SC_TUNE_FP32_CORRELATION  how the FP32 encoder computes alpha0 = D^T x for
+ *     a tile of 16 signals: SC_CORR_MFMA (FP32 matrix cores, default) or
+ *     SC_CORR_VALU (FP32 FMAs).
+ */
+#define SC_TUNE_FP32_CORRELATION 1
+#define SC_CORR_VALU 0
+#define SC_CORR_MFMA 1
+int sc_dict_set_tuning(sc_dict h, int key, int value);
+int sc_dict_get_tuning(sc_dict h, int key, int *value);
+
+/*
  * sc_omp_stats -- counters accumulated by the encoders of this handle since
  * the last reset: stats[0] = signals encoded, stats[1] = total atoms
  * selected, stats[2] = supports refit in FP64, stats[3] = signals sent to the
@@ -166,6 +179,140 @@ int sc_omp_stats(sc_dict h, int64_t stats[4], int reset, void *stream);
 int sc_sh_eval_sparse(sc_dict h, const int32_t *idx, const float *coef, const int32_t *count,
                       int64_t N, int k, const float *dirs, int64_t M, int dir_mode, float *rgb,
                       void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Learned support proposer (an addition to the paper's method)         */
+/* ------------------------------------------------------------------ */
+/*
+ * A small MLP proposes, for each signal, the candidate atoms among which OMP
+ * is then run; the full OMP of Sec. 2.1 stays the fallback whenever the
+ * restricted code's residual exceeds eps, so the result always meets the
+ * paper's stop rule or equals the plain encoder's.  Network:
+ *   xh = x / ||x|| (0 for x = 0),  h1 = GELU(W1 xh + b1),  h2 = GELU(W2 h1 + b2),
+ *   z = W3 h2 + b3  (one logit per atom),  GELU(t) = t Phi(t) (exact, erf form),
+ * BF16 weights and activations with FP32 accumulation on MFMA.
+ * Parameters are one FP32 vector (the master copy), in this order:
+ *   W1 (H x d row-major), b1 (H), W2 (H x H), b2 (H), W3 (K x H), b3 (K).
+ * Supported shapes: d <= 48, H = 256, K in {128, 256, 512}.
+ */
+
+/* Number of FP32 parameters of a d -> H -> H -> K proposer (negative on bad sizes). */
+int64_t sc_proposer_num_params(int d, int H, int K);
+
+/* Create a proposer; parameters start at zero (set them before use).
+ * Errors: SC_EINVAL, SC_ENOMEM, SC_ENODEV. */
+int sc_proposer_create(int d, int H, int K, sc_proposer *out);
+
+/* Release a proposer (waits for the device).  NULL is accepted. */
+int sc_proposer_destroy(sc_proposer p);
+
+/* Dimensions and parameter count of a proposer. */
+int sc_proposer_dims(sc_proposer p, int *d, int *H, int *K, int64_t *nparams);
+
+/* Copy nparams FP32 parameters from device memory into the proposer, refresh
+ * its BF16 copies and reset the optimiser state.  Stream-ordered. */
+int sc_proposer_set_params(sc_proposer p, const float *params, void *stream);
+
+/* Copy the FP32 master parameters out to device memory.  Stream-ordered. */
+int sc_proposer_get_params(sc_proposer p, float *params, void *stream);
+
+/*
+ * sc_proposer_forward -- candidates of N signals.
+ *   X       device N x d float32
+ *   n_cand  1 <= n_cand <= min(32, K)
+ *   cand    device N x n_cand int32 out: the n_cand atoms with the largest
+ *           logits (ties to the lower index), listed in increasing atom
+ *           index; a row of -1 when the input is not finite or when more than
+ *           64 logits tie at the selection threshold (no candidates: the
+ *           learned encoder then uses the full OMP for that signal)
+ *   logits  device N x K float32 out, or NULL (the FP32 logits, for tests)
+ */
+int sc_proposer_forward(sc_proposer p, const float *X, int64_t N, int n_cand, int32_t *cand, float *logits,
+                        void *stream);
+
+/* Bytes of device workspace sc_omp_encode_learned needs for N signals. */
+size_t sc_omp_encode_learned_workspace(int64_t N, int n_cand);
+
+/*
+ * sc_omp_encode_learned -- proposer-guided OMP with the full OMP as fallback.
+ *
+ * 1. candidates = the proposer's n_cand largest logits per signal;
+ * 2. Batch-OMP restricted to the candidates, same stop rule as sc_omp_encode;
+ * 3. explicit FP32 residual ||x - D_I coef||: accepted if <= eps (or
+ *    eps ||x|| with SC_EPS_RELATIVE), else the signal is re-encoded by the
+ *    plain FP32 encoder of sc_omp_encode (counted in sc_omp_stats[3]).
+ * Outputs and per-signal status as sc_omp_encode.  eps = 0 sends every
+ * signal that is not represented exactly to the fallback.
+ *   k        1 <= k <= min(K, d, 16);  n_cand: k <= n_cand <= min(32, K)
+ *   flags    SC_EPS_RELATIVE, SC_NO_FP64_REFIT, SC_PREC_BF16 (the fallback
+ *            encoder then runs in the BF16 precision form)
+ *   workspace  device, >= sc_omp_encode_learned_workspace(N, n_cand) bytes,
+ *              caller-owned, contents overwritten
+ * Requires the proposer's d and K to match the dictionary, d <= 48.
+ * Errors: SC_EINVAL, SC_ENOMEM (workspace too small), SC_EDEVICE.
+ */
+int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, int k, float eps, int flags,
+                          int n_cand, int32_t *idx, float *coef, int32_t *count, float *resid, void *workspace,
+                          size_t ws_bytes, void *stream);
+
+/*
+ * sc_omp_encode_restricted -- step 2 and 3 of sc_omp_encode_learned on their
+ * own: Batch-OMP of each signal restricted to its candidate atoms (cand,
+ * N x n_cand, sorted by atom index, a row starting with -1 = no candidates),
+ * explicit-residual acceptance; accepted codes are written to idx/coef/
+ * count/resid, the other signals' indices are appended to miss_rows
+ * (device int32[N]) and counted in *miss_count (device int32, zeroed by the
+ * call).  Same limits as sc_omp_encode_learned.
+ */
+int sc_omp_encode_restricted(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, const int32_t *cand,
+                             int n_cand, int32_t *idx, float *coef, int32_t *count, float *resid, int32_t *miss_rows,
+                             int32_t *miss_count, void *stream);
+
+/*
+ * sc_omp_encode_rows -- the plain FP32 encoder of sc_omp_encode applied to
+ * the rows listed in rows[0 .. *nrows) of X (nrows is a DEVICE int32, read by
+ * the kernel, so the list can come from sc_omp_encode_restricted without a
+ * host round trip); outputs are written at those rows.  max_rows bounds
+ * *nrows (it sizes the launch).
+ */
+int sc_omp_encode_rows(sc_dict h, const float *X, const int32_t *rows, const int32_t *nrows, int64_t max_rows, int k,
+                       float eps, int flags, int32_t *idx, float *coef, int32_t *count, float *resid, void *stream);
+
+/* ---- proposer training ---- */
+#define SC_TRAIN_FP32      0x1  /* FP32 operands on FP32 MFMA (gradient checks); BF16 otherwise */
+#define SC_TRAIN_GRAD_ONLY 0x2  /* compute the gradients, do not update the parameters        */
+
+/* Bytes of device workspace one training step with batch B needs. */
+size_t sc_proposer_train_workspace(sc_proposer p, int64_t B);
+
+/*
+ * sc_proposer_train_step -- one Adam step on a batch of (signal, OMP support)
+ * pairs.
+ *
+ * Loss: the mean over the B x K entries of the binary cross-entropy on
+ * logits, w y softplus(-z) + (1 - y) softplus(z), with y the multi-hot
+ * indicator of the signal's support (the atoms OMP selected) and w =
+ * pos_weight.  Backpropagation through the three layers (GELU' exact), then
+ * Adam with bias correction (step counter kept in the handle, reset by
+ * sc_proposer_set_params), then the BF16 copies are refreshed.
+ *
+ *   X          device N x d float32 training signals
+ *   rows       device int32[B]: the batch is X[rows[b]] (NULL: rows 0..B-1)
+ *   B          batch size, a positive multiple of 32
+ *   sup_idx    device N x kcap int32 supports (as written by sc_omp_encode)
+ *   sup_count  device int32[N] support sizes (entries < 0 count as empty)
+ *   lr, beta1, beta2, adam_eps   Adam hyper-parameters
+ *   flags      SC_TRAIN_FP32, SC_TRAIN_GRAD_ONLY
+ *   loss_out   device float, or NULL: the batch loss (before the update)
+ *   grads_out  device float[nparams], or NULL: the gradient (parameter order)
+ *   workspace  device, >= sc_proposer_train_workspace(p, B) bytes
+ * Stream-ordered; no allocation.
+ * Errors: SC_EINVAL, SC_ENOMEM (workspace too small), SC_EDEVICE.
+ */
+int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, int64_t B, const int32_t *sup_idx,
+                           const int32_t *sup_count, int kcap, float lr, float beta1, float beta2, float adam_eps,
+                           float pos_weight, int flags, float *loss_out, float *grads_out, void *workspace,
+                           size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -39,7 +39,7 @@ def _load():
     lib = C.CDLL(_SO)
     P = C.c_void_p
     lib.orc_omp.argtypes = [P, C.c_int, C.c_int, P, C.c_int64, C.c_int, C.c_double, C.c_int,
-                            P, C.c_int, P, P, P, P, P, P, C.c_int]
+                            P, C.c_int, P, P, P, P, P, P, P, C.c_int]
     lib.orc_omp.restype = C.c_int
     lib.orc_sh_basis.argtypes = [P, C.c_int64, C.c_int, P]
     lib.orc_sh_basis.restype = None
@@ -66,7 +66,8 @@ def omp(D, X, k, eps=0.0, relative=False, nthreads=None, with_margin=False, cand
     D: (K, d) float32 atom-major; X: (N, d) float32.  Returns dict with
     idx (N,k) int32 in selection order (-1 padded), coef (N,k) float64,
     count (N,) int32, resid (N,) float64 = ||x - D_I gamma||_2 and, if asked,
-    margin (N,) = min over steps of (|c|_(1) - |c|_(2)) / ||r||, and rpath
+    margin (N,) = min over steps of (|c|_(1) - |c|_(2)) / ||r|| and gap (N,)
+    = min over steps of |c|_(1) - |c|_(2), and rpath
     (N, k+1): the residual norm before each selection and at the end.
     cand: optional (N, n_cand) int32 -- restrict each signal's pursuit to
     its listed atoms."""
@@ -81,6 +82,7 @@ def omp(D, X, k, eps=0.0, relative=False, nthreads=None, with_margin=False, cand
     count = np.empty(N, np.int32)
     resid = np.empty(N, np.float64)
     margin = np.empty(N, np.float64) if with_margin else None
+    gap = np.empty(N, np.float64) if with_margin else None
     rpath = np.empty((N, k + 1), np.float64) if with_path else None
     n_cand = 0
     if cand is not None:
@@ -88,12 +90,13 @@ def omp(D, X, k, eps=0.0, relative=False, nthreads=None, with_margin=False, cand
         assert cand.shape[0] == N
         n_cand = cand.shape[1]
     rc = lib.orc_omp(_p(D), d, K, _p(X), N, int(k), float(eps), int(bool(relative)), _p(cand), n_cand,
-                     _p(idx), _p(coef), _p(count), _p(resid), _p(margin), _p(rpath), _threads(nthreads))
+                     _p(idx), _p(coef), _p(count), _p(resid), _p(margin), _p(rpath), _p(gap), _threads(nthreads))
     if rc != 0:
         raise ValueError("orc_omp: invalid arguments")
     out = dict(idx=idx, coef=coef, count=count, resid=resid)
     if with_margin:
         out["margin"] = margin
+        out["gap"] = gap
     if with_path:
         out["rpath"] = rpath
     return out

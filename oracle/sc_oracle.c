@@ -98,6 +98,7 @@ typedef struct {
     double *resid;
     double *margin;       /* optional: min over steps of (|c|_(1)-|c|_(2))/||r|| */
     double *rpath;        /* optional N x (k+1): ||r|| after 0..count atoms, NaN after */
+    double *gap;          /* optional: min over steps of |c|_(1) - |c|_(2) (absolute) */
     int64_t lo, hi;
 } omp_job;
 
@@ -123,6 +124,7 @@ static void omp_one(const omp_job *J, int64_t s, double *ws, unsigned char *used
         J->count[s] = -1;
         J->resid[s] = NAN;
         if (J->margin) J->margin[s] = NAN;
+        if (J->gap) J->gap[s] = NAN;
         return;
     }
     double xn = 0.0;
@@ -135,7 +137,7 @@ static void omp_one(const omp_job *J, int64_t s, double *ws, unsigned char *used
     memcpy(r, x, sizeof(double) * d);
     memset(used, 0, (size_t)J->K);
     int n = 0;
-    double marg = INFINITY;
+    double marg = INFINITY, gmin = INFINITY;
     for (;;) {
         double rn = 0.0;
         for (int i = 0; i < d; ++i) rn += r[i] * r[i];
@@ -162,6 +164,7 @@ static void omp_one(const omp_job *J, int64_t s, double *ws, unsigned char *used
         if (best < 0 || bv <= 1e-14 * xn) break;
         double m = (bv - sv) / rn;
         if (m < marg) marg = m;
+        if (bv - sv < gmin) gmin = bv - sv;
         used[best] = 1;
         I[n] = best;
         memcpy(A + (size_t)n * d, J->D + (size_t)best * d, sizeof(double) * d);
@@ -186,6 +189,7 @@ static void omp_one(const omp_job *J, int64_t s, double *ws, unsigned char *used
     J->count[s] = n;
     J->resid[s] = sqrt(rr);
     if (J->margin) J->margin[s] = marg;
+    if (J->gap) J->gap[s] = gmin;
 }
 
 static void *omp_worker(void *arg)
@@ -208,11 +212,13 @@ static void *omp_worker(void *arg)
  * Outputs: idx N x k (selection order, -1 padded), coef N x k (0 padded),
  * count N, resid N (explicit ||x - D_I gamma||), margin N (optional, may be
  * NULL), rpath N x (k+1) (optional: the residual norm before each selection
- * and at the end, NaN past the end).  Returns 0, or -1 on bad arguments.
+ * and at the end, NaN past the end), gap N (optional: min over steps of the
+ * absolute gap between the two largest |correlations|).  Returns 0, or -1 on
+ * bad arguments.
  */
 int orc_omp(const float *D_atoms, int d, int K, const float *X, int64_t N, int k, double eps,
             int relative, const int32_t *cand, int n_cand, int32_t *idx, double *coef,
-            int32_t *count, double *resid, double *margin, double *rpath, int nthreads)
+            int32_t *count, double *resid, double *margin, double *rpath, double *gap, int nthreads)
 {
     if (d <= 0 || K <= 0 || k <= 0 || k > d || N < 0 || !(eps >= 0.0)) return -1;
     if (cand && n_cand <= 0) return -1;
@@ -224,7 +230,7 @@ int orc_omp(const float *D_atoms, int d, int K, const float *X, int64_t N, int k
     omp_job *jobs = (omp_job *)malloc(sizeof(omp_job) * nthreads);
     for (int t = 0; t < nthreads; ++t) {
         omp_job J = {Dd, d, K, k, eps, relative, X, cand, n_cand, idx, coef, count, resid, margin,
-                     rpath, N * t / nthreads, N * (t + 1) / nthreads};
+                     rpath, gap, N * t / nthreads, N * (t + 1) / nthreads};
         jobs[t] = J;
         pthread_create(&th[t], NULL, omp_worker, &jobs[t]);
     }

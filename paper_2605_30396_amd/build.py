@@ -23,6 +23,7 @@ CXXFLAGS = [
     "-fPIC",
     "-std=c++17",
     "-Wno-unused-result",
+    "-Wno-unused-value",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

@@ -1,0 +1,347 @@
+// Learned support proposer, inference: a 3-layer MLP d -> 256 -> 256 -> K
+// (GELU, BF16 weights and activations, FP32 accumulation on MFMA) fused with
+// the exact selection of each signal's n_cand largest logits.
+//
+// Workgroup = 8 waves, tile = 64 signals.  The three layers are computed as
+// Z^T = W H^T with v_mfma_f32_32x32x16_bf16: the A operand is a 32 x 16 block
+// of the weight matrix read straight from global memory (L2-resident), the B
+// operand comes from the activation tile in LDS.  Wave w owns N-tile (32
+// signals) w & 1 and the M-tiles (32 outputs) w/2, w/2 + 4, ...; each weight
+// is read once per tile.  In the MFMA output layout a lane holds 16 outputs
+// of one signal, so the selection needs no transpose:
+//   1. each lane takes maxima of groups of 4*KT of its logits: 32 group
+//      maxima per signal;
+//   2. theta = the n_cand-th largest group maximum is a safe lower bound of
+//      the n_cand-th largest logit (n_cand groups reach it);
+//   3. each of the signal's 8 writer lanes appends its logits >= theta to a
+//      private 16-slot list, as keys that order like the logit, with the
+//      atom index in the low bits (unique keys, lower index wins a tie);
+//   4. one wave per signal finds the n_cand-th largest key by a bitwise
+//      search with ballot counts, marks the chosen atoms in a bit mask and
+//      writes them in increasing atom index.
+// A signal whose lists overflow (ties of many logits at the threshold) or
+// whose input is not finite gets candidate list {-1, ...}: the encoder then
+// sends it straight to the full-OMP fallback.  Keys keep the top 32 - IB bits
+// of the order-preserving FP32 key (IB = 7, 8, 9 index bits for K = 128, 256,
+// 512), so logits closer than ~2^(IB-23) relative count as ties.
+#include "mfma.h"
+#include "sc_internal.h"
+#include "wave.h"
+
+namespace sc {
+
+constexpr int kPT = 64;        // signals per tile
+constexpr int kPWaves = 8;
+constexpr int kPThreads = 64 * kPWaves;
+constexpr int kPH = 256;       // hidden width
+constexpr int kXS = 72;        // LDS row stride (bf16) of the input tile
+constexpr int kHS = 264;       // LDS row stride (bf16) of a hidden tile
+constexpr int kNG = 32;        // group maxima per signal
+constexpr int kWriters = 8;    // lanes holding logits of one signal
+constexpr int kSlots = 16;     // candidate slots per writer lane
+
+constexpr int kXBytes = kPT * kXS * 2;        //  9216
+constexpr int kHBytes = kPT * kHS * 2;        // 33792
+constexpr int kPropLds = kXBytes + 2 * kHBytes + kPT * 4;
+
+// Sort n = 32 floats descending in registers (bitonic network).
+__device__ __forceinline__ void sort32_desc(float *v) {
+#pragma unroll
+    for (int k = 2; k <= 32; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                int p = i ^ j;
+                if (p > i) {
+                    bool desc = (i & k) == 0;
+                    float a = v[i], b = v[p];
+                    float hi = fmaxf(a, b), lo = fminf(a, b);
+                    v[i] = desc ? hi : lo;
+                    v[p] = desc ? lo : hi;
+                }
+            }
+}
+
+// One hidden layer for the 64-signal tile: Hout = GELU(W Hin^T + b)^T (BF16),
+// 256 outputs; wave w computes N-tile w & 1, M-tiles w/2 and w/2 + 4.
+__device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int ldw, int kin,
+                                            const float *__restrict__ bias, const uint16_t *__restrict__ Hin, int ldh,
+                                            uint16_t *__restrict__ Hout, int wave, int lane) {
+    const int nt = wave & 1, m0 = wave >> 1;
+    floatx16 acc[2] = {floatx16{}, floatx16{}};
+    const int lr = lane & 31, lk = 8 * (lane >> 5);
+#pragma unroll 2
+    for (int ks = 0; ks < kin; ks += 16) {
+        const bf16x8 b = ld_bf16x8(Hin + (32 * nt + lr) * ldh + ks + lk);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const bf16x8 a = ld_bf16x8(W + (size_t)(32 * (m0 + 4 * q) + lr) * ldw + ks + lk);
+            acc[q] = mfma32(a, b, acc[q]);
+        }
+    }
+    const int j = 32 * nt + lr;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int i0 = 32 * (m0 + 4 * q) + 8 * g + 4 * (lane >> 5);
+            const float4 bb = *reinterpret_cast<const float4 *>(bias + i0);
+            uint32_t h0 = bf16_bits(gelu_f(acc[q][4 * g + 0] + bb.x));
+            uint32_t h1 = bf16_bits(gelu_f(acc[q][4 * g + 1] + bb.y));
+            uint32_t h2 = bf16_bits(gelu_f(acc[q][4 * g + 2] + bb.z));
+            uint32_t h3 = bf16_bits(gelu_f(acc[q][4 * g + 3] + bb.w));
+            uint2 pk;
+            pk.x = h0 | (h1 << 16);
+            pk.y = h2 | (h3 << 16);
+            *reinterpret_cast<uint2 *>(Hout + j * kHS + i0) = pk;
+        }
+}
+
+template <int KT>
+__global__ __launch_bounds__(kPThreads) void proposer_topk_kernel(PropDev P, const float *__restrict__ X, int64_t N,
+                                                                  int n_cand, int32_t *__restrict__ cand,
+                                                                  float *__restrict__ logits) {
+    constexpr int K = 128 * KT;     // outputs (= dictionary atoms)
+    constexpr int GS = 4 * KT;      // logits per group maximum
+    constexpr int IB = KT == 1 ? 7 : (KT == 2 ? 8 : 9);   // index bits in a key
+    constexpr uint32_t IMASK = (1u << IB) - 1u;
+    constexpr int MW = K / 32;      // mask words per signal
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint16_t *Xh = reinterpret_cast<uint16_t *>(lds);
+    uint16_t *H1 = reinterpret_cast<uint16_t *>(lds + kXBytes);
+    uint16_t *H2 = reinterpret_cast<uint16_t *>(lds + kXBytes + kHBytes);
+    int *bad = reinterpret_cast<int *>(lds + kXBytes + 2 * kHBytes);
+    // reused once the first two layers are done (Xh and H1 are dead then)
+    float *gmax = reinterpret_cast<float *>(lds);                            // [64][32]
+    float *theta = gmax + kPT * kNG;                                          // [64]
+    uint32_t *mask = reinterpret_cast<uint32_t *>(theta + kPT);              // [8 waves][16]
+    uint8_t *wcnt = reinterpret_cast<uint8_t *>(mask + kPWaves * 16);        // [64][8]
+    uint32_t *slots = reinterpret_cast<uint32_t *>(wcnt + kPT * kWriters);   // [64][8][16]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int d = P.d;
+    const int lr = lane & 31, lk = 8 * (lane >> 5);
+    const int64_t ntiles = (N + kPT - 1) / kPT;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t s0 = tile * kPT;
+        const int nt_sig = (int)min<int64_t>(kPT, N - s0);
+        __syncthreads();
+        // ---- input tile: x / ||x|| in BF16, zero padded to 64 features ----
+        {
+            const int s = tid >> 3, q = tid & 7;
+            float xv[8];
+            float ss = 0.f;
+            bool fin = true;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int f = q + 8 * m;
+                float v = 0.f;
+                if (s < nt_sig && f < d) v = X[(s0 + s) * d + f];
+                fin &= isfinite(v);
+                xv[m] = v;
+                ss = fmaf(v, v, ss);
+            }
+            ss += dpp_f<SC_DPP_QP1032>(ss);
+            ss += dpp_f<SC_DPP_QP2301>(ss);
+            ss += dpp_f<SC_DPP_HMIRROR>(ss);
+            int nf = fin ? 0 : 1;
+            nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_QP1032, 0xF, 0xF, false);
+            nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_QP2301, 0xF, 0xF, false);
+            nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_HMIRROR, 0xF, 0xF, false);
+            const float nrm = sqrtf(ss);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int f = q + 8 * m;
+                const float v = (nrm > 0.f && !nf) ? xv[m] / nrm : 0.f;
+                Xh[s * kXS + f] = bf16_bits(v);
+            }
+            if (q == 0) bad[s] = (s >= nt_sig) || nf;
+        }
+        __syncthreads();
+        dense_layer(P.W1b, 64, 64, P.b1, Xh, kXS, H1, wave, lane);
+        __syncthreads();
+        dense_layer(P.W2b, kPH, kPH, P.b2, H1, kHS, H2, wave, lane);
+        __syncthreads();
+        // ---- layer 3: logits, N-tile wave & 1, M-tiles wave/2 + 4q ----
+        const int nt = wave & 1, m0 = wave >> 1;
+        const int j = 32 * nt + lr;                 // this lane's signal in the tile
+        const int wr = m0 * 2 + (lane >> 5);        // writer index of the lane for signal j
+        floatx16 acc[KT];
+#pragma unroll
+        for (int q = 0; q < KT; ++q) acc[q] = floatx16{};
+#pragma unroll 2
+        for (int ks = 0; ks < kPH; ks += 16) {
+            const bf16x8 b = ld_bf16x8(H2 + j * kHS + ks + lk);
+#pragma unroll
+            for (int q = 0; q < KT; ++q) {
+                const bf16x8 a = ld_bf16x8(P.W3b + (size_t)(32 * (m0 + 4 * q) + lr) * kPH + ks + lk);
+                acc[q] = mfma32(a, b, acc[q]);
+            }
+        }
+        // bias, optional logits, group maxima
+#pragma unroll
+        for (int q = 0; q < KT; ++q) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int i0 = 32 * (m0 + 4 * q) + 8 * g + 4 * (lane >> 5);
+                const float4 bb = *reinterpret_cast<const float4 *>(P.b3 + i0);
+                acc[q][4 * g + 0] += bb.x;
+                acc[q][4 * g + 1] += bb.y;
+                acc[q][4 * g + 2] += bb.z;
+                acc[q][4 * g + 3] += bb.w;
+                if (logits && j < nt_sig) {
+                    float4 o = {acc[q][4 * g], acc[q][4 * g + 1], acc[q][4 * g + 2], acc[q][4 * g + 3]};
+                    *reinterpret_cast<float4 *>(logits + (s0 + j) * K + i0) = o;
+                }
+            }
+#pragma unroll
+            for (int gg = 0; gg < 16 / GS; ++gg) {
+                float mx = acc[q][gg * GS];
+#pragma unroll
+                for (int r = 1; r < GS; ++r) mx = fmaxf(mx, acc[q][gg * GS + r]);
+                gmax[j * kNG + (wr * KT + q) * (16 / GS) + gg] = mx;
+            }
+        }
+        __syncthreads();
+        // ---- safe threshold per signal ----
+        if (tid < kPT) {
+            float v[32];
+#pragma unroll
+            for (int g = 0; g < 32; ++g) v[g] = gmax[tid * kNG + g];
+            sort32_desc(v);
+            float th = v[0];
+#pragma unroll
+            for (int g = 0; g < 32; ++g)
+                if (g == n_cand - 1) th = v[g];
+            theta[tid] = bad[tid] ? __builtin_inff() : th;
+        }
+        __syncthreads();
+        // ---- candidates above the threshold, into private slots ----
+        {
+            const float th = theta[j];
+            uint32_t *myslots = slots + (j * kWriters + wr) * kSlots;
+            int cnt = 0;
+#pragma unroll
+            for (int q = 0; q < KT; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float z = acc[q][r];
+                    if (z >= th) {
+                        const int i = 32 * (m0 + 4 * q) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        if (cnt < kSlots) myslots[cnt] = (order_key(z) & ~IMASK) | (IMASK - (uint32_t)i);
+                        ++cnt;
+                    }
+                }
+            wcnt[j * kWriters + wr] = (uint8_t)min(cnt, 255);
+        }
+        __syncthreads();
+        // ---- exact top-n_cand per signal (one wave per signal) ----
+        for (int s = wave; s < nt_sig; s += kPWaves) {
+            int32_t *out = cand + (s0 + s) * n_cand;
+            int wc = lane < kWriters ? (int)wcnt[s * kWriters + lane] : 0;
+            const bool over = __ballot(lane < kWriters && wc > kSlots) != 0;
+            // lane i takes slots i and i + 64 (writer = slot / 16)
+            uint32_t k0 = 0, k1 = 0;
+            {
+                const int q0 = lane, q1 = lane + 64;
+                const int c0 = wcnt[s * kWriters + (q0 >> 4)], c1 = wcnt[s * kWriters + (q1 >> 4)];
+                if ((q0 & 15) < c0 && (q0 & 15) < kSlots) k0 = slots[s * kWriters * kSlots + q0];
+                if ((q1 & 15) < c1 && (q1 & 15) < kSlots) k1 = slots[s * kWriters * kSlots + q1];
+            }
+            const int total = __popcll(__ballot(k0 != 0)) + __popcll(__ballot(k1 != 0));
+            if (bad[s] || over || total < n_cand) {
+                if (lane < n_cand) out[lane] = -1;
+                continue;
+            }
+            // largest tau with #{key >= tau} >= n_cand: the n_cand-th largest key
+            uint32_t tau = 0;
+            for (int bit = 31; bit >= 0; --bit) {
+                const uint32_t t2 = tau | (1u << bit);
+                const int c = __popcll(__ballot(k0 >= t2)) + __popcll(__ballot(k1 >= t2));
+                if (c >= n_cand) tau = t2;
+            }
+            // mark the chosen atoms, then list them in increasing index
+            uint32_t *mw = mask + wave * 16;
+            if (lane < MW) mw[lane] = 0u;
+            __builtin_amdgcn_wave_barrier();
+            if (k0 >= tau && k0 != 0) {
+                const uint32_t i = IMASK - (k0 & IMASK);
+                atomicOr(&mw[i >> 5], 1u << (i & 31));
+            }
+            if (k1 >= tau && k1 != 0) {
+                const uint32_t i = IMASK - (k1 & IMASK);
+                atomicOr(&mw[i >> 5], 1u << (i & 31));
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < MW) {
+                uint32_t word = mw[lane];
+                int pos = 0;
+                for (int v = 0; v < lane; ++v) pos += __popc(mw[v]);
+                while (word) {
+                    const int bpos = __ffs(word) - 1;
+                    out[pos++] = 32 * lane + bpos;
+                    word &= word - 1u;
+                }
+            }
+        }
+    }
+}
+
+// FP32 master parameters -> BF16 MFMA copies (W1 padded to 64 inputs).
+__global__ void proposer_pack_kernel(const float *__restrict__ params, int d, int H, int K, uint16_t *__restrict__ W1b,
+                                     uint16_t *__restrict__ W2b, uint16_t *__restrict__ W3b) {
+    const int64_t n1 = (int64_t)H * 64, n2 = (int64_t)H * H, n3 = (int64_t)K * H;
+    const float *W1 = params;
+    const float *W2 = W1 + (size_t)H * d + H;
+    const float *W3 = W2 + (size_t)H * H + H;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n1 + n2 + n3;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < n1) {
+            int i = (int)(t / 64), f = (int)(t % 64);
+            W1b[t] = bf16_bits(f < d ? W1[(size_t)i * d + f] : 0.f);
+        } else if (t < n1 + n2) {
+            W2b[t - n1] = bf16_bits(W2[t - n1]);
+        } else {
+            W3b[t - n1 - n2] = bf16_bits(W3[t - n1 - n2]);
+        }
+    }
+}
+
+hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16_t *W1b, uint16_t *W2b,
+                                uint16_t *W3b, hipStream_t st) {
+    proposer_pack_kernel<<<1024, 256, 0, st>>>(params, d, H, K, W1b, W2b, W3b);
+    return hipGetLastError();
+}
+
+template <int KT>
+static hipError_t launch_topk_t(const PropDev &P, const float *X, int64_t N, int n_cand, int32_t *cand,
+                                float *logits, hipStream_t st) {
+    auto kern = proposer_topk_kernel<KT>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kPropLds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t ntiles = (N + kPT - 1) / kPT;
+    const int64_t grid = std::min<int64_t>(ntiles, (int64_t)ncu * 2);   // two 77 KB tiles per CU
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kPThreads), kPropLds, st, P, X, N, n_cand, cand, logits);
+    return hipGetLastError();
+}
+
+hipError_t launch_proposer_topk(const PropDev &P, const float *X, int64_t N, int n_cand, int32_t *cand,
+                                float *logits, hipStream_t st) {
+    if (P.H != kPH || P.d > 64 || n_cand < 1 || n_cand > kNG) return hipErrorInvalidValue;
+    switch (P.K) {
+        case 128: return launch_topk_t<1>(P, X, N, n_cand, cand, logits, st);
+        case 256: return launch_topk_t<2>(P, X, N, n_cand, cand, logits, st);
+        case 512: return launch_topk_t<4>(P, X, N, n_cand, cand, logits, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sc

@@ -1,0 +1,381 @@
+// Restricted Batch-OMP over per-signal candidate atoms (the proposer's list),
+// with the explicit-residual acceptance test that routes misses to the full
+// encoder.
+//
+// Eight lanes serve one signal (8 signals per wave); lane g of a group owns
+// candidates 4g .. 4g+3 of the signal's list, which is sorted by atom index,
+// so the lowest (lane, entry) with the largest |alpha| is the lowest atom
+// index.  Group reductions use DPP inside each 8-lane half-row; values of the
+// winning lane are fetched with ds_bpermute.  The pursuit is the same
+// Batch-OMP as the full encoder (alpha0 = D_C^T x, Gram-row update of the
+// orthonormalised correlations, incremental Cholesky), restricted to C.
+//
+// After the pursuit the coefficients are solved, the residual ||x - D_I g|| is
+// computed explicitly in FP32, and the code is accepted if it is <= eps (or
+// eps ||x||); otherwise the signal index is appended to the fallback list.
+#include "sc_internal.h"
+#include "wave.h"
+
+namespace sc {
+
+constexpr int kRCpl = 4;           // candidates per lane (n_cand <= 32)
+constexpr int kRThreads = 256;
+
+template <int KMAX>
+struct GroupScratch {
+    float L[KMAX * KMAX];
+    float c[KMAX];
+    float gam[KMAX];
+    int sel[KMAX];
+    float x[48];
+};
+
+template <int KMAX>
+struct RompWaveScratch {
+    GroupScratch<KMAX> g[8];
+    double Gd[KMAX * KMAX];
+    double zd[KMAX];
+};
+
+__device__ __forceinline__ float grp_max(float v) {
+    v = fmaxf(v, dpp_f<SC_DPP_QP1032>(v));
+    v = fmaxf(v, dpp_f<SC_DPP_QP2301>(v));
+    v = fmaxf(v, dpp_f<SC_DPP_HMIRROR>(v));
+    return v;
+}
+
+__device__ __forceinline__ float grp_sum(float v) {
+    v += dpp_f<SC_DPP_QP1032>(v);
+    v += dpp_f<SC_DPP_QP2301>(v);
+    v += dpp_f<SC_DPP_HMIRROR>(v);
+    return v;
+}
+
+__device__ __forceinline__ float shfl_f(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ int shfl_i(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+
+template <int N>
+using vecr = float __attribute__((ext_vector_type(N)));
+
+// gamma = L^-T c (group lane 0).
+template <int KMAX>
+__device__ __forceinline__ void grp_back_substitute(GroupScratch<KMAX> &gs, int n, int g) {
+    __builtin_amdgcn_wave_barrier();
+    if (g == 0) {
+        for (int t = n - 1; t >= 0; --t) {
+            float s = gs.c[t];
+            for (int u = t + 1; u < n; ++u) s -= gs.L[u * KMAX + t] * gs.gam[u];
+            gs.gam[t] = s / gs.L[t * KMAX + t];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ||x - D_I gamma||^2 over the group (lane g holds features g, g+8, ...).
+template <int KMAX>
+__device__ __forceinline__ float grp_resid2(const GroupScratch<KMAX> &gs, int n, const float *__restrict__ D48, int d,
+                                            int g) {
+    float acc = 0.f;
+    for (int f = g; f < d; f += 8) {
+        float r = gs.x[f];
+        for (int t = 0; t < n; ++t) r -= D48[(size_t)gs.sel[t] * 48 + f] * gs.gam[t];
+        acc = fmaf(r, r, acc);
+    }
+    return grp_sum(acc);
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict, const float *__restrict__ D48,
+                                                                    RompParams p) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    RompWaveScratch<KMAX> *wsAll = reinterpret_cast<RompWaveScratch<KMAX> *>(smem_raw);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane & 7, grp = lane >> 3;
+    RompWaveScratch<KMAX> &ws = wsAll[wave];
+    GroupScratch<KMAX> &gs = ws.g[grp];
+    const int d = dict.d, Kp = dict.Kp, k = p.k, nc = p.n_cand;
+    const float *__restrict__ G = dict.G;
+    const float nanv = __builtin_nanf("");
+    unsigned long long n_sig = 0, n_atoms = 0, n_miss = 0, n_refit = 0;
+    using vR = vecr<kRCpl>;
+
+    const int64_t ngroups = (p.N + 7) / 8;
+    const int64_t gwave = (int64_t)blockIdx.x * (kRThreads / 64) + wave;
+    const int64_t wstride = (int64_t)gridDim.x * (kRThreads / 64);
+    for (int64_t wg = gwave; wg < ngroups; wg += wstride) {
+        const int64_t sig = wg * 8 + grp;
+        const bool valid = sig < p.N;
+        // ---- signal and candidates ----
+        float xx_part = 0.f;
+        bool fin = true;
+        for (int f = g; f < 48; f += 8) {
+            float v = (valid && f < d) ? p.X[sig * d + f] : 0.f;
+            fin &= isfinite(v);
+            gs.x[f] = v;
+            xx_part = fmaf(v, v, xx_part);
+        }
+        int nf = fin ? 0 : 1;
+        nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_QP1032, 0xF, 0xF, false);
+        nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_QP2301, 0xF, 0xF, false);
+        nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_HMIRROR, 0xF, 0xF, false);
+        const float xx = grp_sum(xx_part);
+        int cid[kRCpl];
+        bool cand_ok = true;
+#pragma unroll
+        for (int e = 0; e < kRCpl; ++e) {
+            const int q = g * kRCpl + e;
+            cid[e] = (valid && q < nc) ? p.cand[sig * nc + q] : -1;
+        }
+        {
+            int first = valid ? p.cand[sig * nc] : 0;
+            cand_ok = first >= 0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // ---- alpha0 over the candidates ----
+        vR al;
+#pragma unroll
+        for (int e = 0; e < kRCpl; ++e) al[e] = 0.f;
+#pragma unroll 2
+        for (int f4 = 0; f4 < 12; ++f4) {
+            const float4 xv = *reinterpret_cast<const float4 *>(gs.x + 4 * f4);
+#pragma unroll
+            for (int e = 0; e < kRCpl; ++e) {
+                const int c = cid[e] < 0 ? 0 : cid[e];
+                const float4 dv = *reinterpret_cast<const float4 *>(D48 + (size_t)c * 48 + 4 * f4);
+                al[e] = fmaf(dv.x, xv.x, fmaf(dv.y, xv.y, fmaf(dv.z, xv.z, fmaf(dv.w, xv.w, al[e]))));
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kRCpl; ++e)
+            if (cid[e] < 0) al[e] = nanv;
+
+        const float xnorm = sqrtf(xx);
+        const float eps_abs = p.relative ? p.eps * xnorm : p.eps;
+        const float eps2 = eps_abs * eps_abs;
+        const float band = 1e-5f * xx;
+        const float brk = 1e-6f * xnorm;
+        bool active = valid && !nf && cand_ok && xx > 0.f;
+        bool explicit_done = false;
+        float rr_expl = 0.f;
+        float rr = xx;
+        float lmax = 0.f, lmin = 3.4e38f;
+        int n = 0;
+        vR B[KMAX];
+
+#pragma unroll
+        for (int it = 0; it < KMAX; ++it) {
+            if (active) {
+                bool go = it < k;
+                if (go && eps2 > 0.f) {
+                    if (rr <= eps2 - band) {
+                        go = false;
+                    } else if (rr <= eps2 + band) {
+                        grp_back_substitute<KMAX>(gs, it, g);
+                        float re = grp_resid2<KMAX>(gs, it, D48, d, g);
+                        if (re <= eps2) {
+                            explicit_done = true;
+                            rr_expl = re;
+                            go = false;
+                        }
+                    }
+                }
+                float m = -1.f;
+                int ei = 0;
+#pragma unroll
+                for (int e = 0; e < kRCpl; ++e) {
+                    float v = fabsf(al[e]);
+                    if (v > m) {
+                        m = v;
+                        ei = e;
+                    }
+                }
+                const float mx = grp_max(m);
+                if (go && !(mx > brk)) go = false;
+                const uint64_t bal = __ballot(go && m == mx);
+                const int gbits = (int)((bal >> (grp * 8)) & 0xFFull);
+                const int owner = grp * 8 + (__ffs(gbits) - 1);
+                float myal = al[0];
+                int myc = cid[0];
+#pragma unroll
+                for (int e = 1; e < kRCpl; ++e)
+                    if (ei == e) {
+                        myal = al[e];
+                        myc = cid[e];
+                    }
+                const int es = shfl_i(ei, go ? owner : lane);
+                const int j = shfl_i(myc, go ? owner : lane);
+                const float aj = shfl_f(myal, go ? owner : lane);
+                float wsq = 0.f;
+                float w[KMAX];
+#pragma unroll
+                for (int t = 0; t < it; ++t) {
+                    float bv = B[t][0];
+#pragma unroll
+                    for (int e = 1; e < kRCpl; ++e)
+                        if (es == e) bv = B[t][e];
+                    w[t] = shfl_f(bv, go ? owner : lane);
+                    wsq = fmaf(w[t], w[t], wsq);
+                }
+                if (go) {
+                    const float gjj = G[(size_t)j * Kp + j];
+                    const float l2 = gjj - wsq;
+                    if (!(l2 > 1e-9f * gjj)) {
+                        go = false;
+                    } else {
+                        const float ell = sqrtf(l2);
+                        const float inv = 1.f / ell;
+                        const float cn = aj * inv;
+                        rr = fmaf(-cn, cn, rr);
+                        lmax = fmaxf(lmax, ell);
+                        lmin = fminf(lmin, ell);
+                        vR bn;
+#pragma unroll
+                        for (int e = 0; e < kRCpl; ++e) bn[e] = cid[e] >= 0 ? G[(size_t)j * Kp + cid[e]] : 0.f;
+#pragma unroll
+                        for (int t = 0; t < it; ++t) bn -= w[t] * B[t];
+                        bn *= inv;
+                        B[it] = bn;
+                        al -= cn * bn;
+                        if (lane == owner) {
+#pragma unroll
+                            for (int e = 0; e < kRCpl; ++e)
+                                if (es == e) al[e] = nanv;
+                        }
+                        if (g == 0) {
+                            for (int t = 0; t < it; ++t) gs.L[it * KMAX + t] = w[t];
+                            gs.L[it * KMAX + it] = ell;
+                            gs.c[it] = cn;
+                            gs.sel[it] = j;
+                        }
+                        n = it + 1;
+                    }
+                }
+                active = go;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+
+        // ---- finalise ----
+        grp_back_substitute<KMAX>(gs, n, g);
+        const bool ok_sig = valid && !nf && cand_ok;
+        bool want_refit = ok_sig && n > 0 && p.fp64_refit && (lmax / lmin) * (lmax / lmin) > p.kappa_max;
+        // FP64 refits, one group at a time (rare)
+        uint64_t rb = __ballot(want_refit && g == 0);
+        while (rb) {
+            const int gl = __ffsll((unsigned long long)rb) - 1;
+            rb &= rb - 1;
+            GroupScratch<KMAX> &gq = ws.g[gl >> 3];
+            const int nq = shfl_i(n, gl);
+            for (int q = lane; q < nq * nq; q += 64) {
+                int t = q / nq, u = q % nq;
+                double s = 0.0;
+                for (int i = 0; i < d; ++i)
+                    s += (double)D48[(size_t)gq.sel[t] * 48 + i] * (double)D48[(size_t)gq.sel[u] * 48 + i];
+                ws.Gd[t * KMAX + u] = s;
+            }
+            if (lane < nq) {
+                double s = 0.0;
+                for (int i = 0; i < d; ++i) s += (double)D48[(size_t)gq.sel[lane] * 48 + i] * (double)gq.x[i];
+                ws.zd[lane] = s;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                double *Gd = ws.Gd, *z = ws.zd;
+                for (int t = 0; t < nq; ++t)
+                    for (int u = 0; u <= t; ++u) {
+                        double s = Gd[t * KMAX + u];
+                        for (int v = 0; v < u; ++v) s -= Gd[t * KMAX + v] * Gd[u * KMAX + v];
+                        Gd[t * KMAX + u] = (u == t) ? sqrt(fmax(s, 1e-300)) : s / Gd[u * KMAX + u];
+                    }
+                for (int t = 0; t < nq; ++t) {
+                    double s = z[t];
+                    for (int u = 0; u < t; ++u) s -= Gd[t * KMAX + u] * z[u];
+                    z[t] = s / Gd[t * KMAX + t];
+                }
+                for (int t = nq - 1; t >= 0; --t) {
+                    double s = z[t];
+                    for (int u = t + 1; u < nq; ++u) s -= Gd[u * KMAX + t] * z[u];
+                    z[t] = s / Gd[t * KMAX + t];
+                }
+                for (int t = 0; t < nq; ++t) gq.gam[t] = (float)z[t];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (want_refit) {
+            explicit_done = false;
+            if (g == 0) n_refit += 1;
+        }
+        float re = grp_resid2<KMAX>(gs, n, D48, d, g);
+        if (explicit_done) re = rr_expl;
+        if (valid) {
+            int32_t *oidx = p.idx + sig * k;
+            float *ocoef = p.coef + sig * k;
+            if (nf) {
+                for (int t = g; t < k; t += 8) {
+                    oidx[t] = -1;
+                    ocoef[t] = 0.f;
+                }
+                if (g == 0) {
+                    p.count[sig] = -1;
+                    if (p.resid) p.resid[sig] = nanv;
+                }
+            } else if (cand_ok && (re <= eps2 || xx == 0.f)) {
+                for (int t = g; t < k; t += 8) {
+                    oidx[t] = t < n ? gs.sel[t] : -1;
+                    ocoef[t] = t < n ? gs.gam[t] : 0.f;
+                }
+                if (g == 0) {
+                    p.count[sig] = n;
+                    if (p.resid) p.resid[sig] = sqrtf(re);
+                    n_sig += 1;
+                    n_atoms += n;
+                }
+            } else if (g == 0) {
+                const int pos = atomicAdd(p.miss_count, 1);
+                p.miss_rows[pos] = (int32_t)sig;
+                n_miss += 1;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (p.stats && g == 0 && (n_sig | n_miss | n_refit)) {
+        atomicAdd(p.stats + 0, n_sig);
+        atomicAdd(p.stats + 1, n_atoms);
+        if (n_refit) atomicAdd(p.stats + 2, n_refit);
+        if (n_miss) atomicAdd(p.stats + 3, n_miss);
+    }
+}
+
+template <int KMAX>
+static hipError_t launch_romp_t(const DictDev &dict, const float *D48, const RompParams &p, hipStream_t st) {
+    const size_t smem = sizeof(RompWaveScratch<KMAX>) * (kRThreads / 64);
+    auto kern = omp_restricted_kernel<KMAX>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t nw = (p.N + 7) / 8;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((nw + 3) / 4, (int64_t)ncu * 8));
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kRThreads), smem, st, dict, D48, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_omp_restricted(const DictDev &dict, const float *D48, const RompParams &p, int kmax, hipStream_t st) {
+    if (p.n_cand > 8 * kRCpl) return hipErrorInvalidValue;
+    switch (kmax) {
+        case 4: return launch_romp_t<4>(dict, D48, p, st);
+        case 8: return launch_romp_t<8>(dict, D48, p, st);
+        case 12: return launch_romp_t<12>(dict, D48, p, st);
+        case 16: return launch_romp_t<16>(dict, D48, p, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sc

@@ -10,6 +10,10 @@
 namespace {
 
 thread_local char g_last_error[512] = "";
+constexpr float kKappaMax = 1e3f;   // Cholesky condition estimate above which supports are refit in FP64
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int set_dev_error(const char *what, hipError_t e) {
     snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
@@ -45,6 +49,8 @@ void free_dict(sc_dict h) {
     hipFree(h->DT);
     hipFree(h->G);
     hipFree(h->Dbf);
+    hipFree(h->Dlo);
+    hipFree(h->D48);
     hipFree(h->status);
     hipFree(h->stats);
     delete h;
@@ -85,6 +91,8 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
               hipMalloc(&h->DT, sizeof(float) * (size_t)d * Kp) == hipSuccess &&
               hipMalloc(&h->G, sizeof(float) * (size_t)K * Kp) == hipSuccess &&
               hipMalloc(&h->Dbf, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
+              hipMalloc(&h->Dlo, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
+              hipMalloc(&h->D48, sizeof(float) * (size_t)K * 48) == hipSuccess &&
               hipMalloc(&h->status, sizeof(int) * 4) == hipSuccess &&
               hipMalloc(&h->stats, sizeof(unsigned long long) * 4) == hipSuccess;
     if (!ok) {
@@ -110,13 +118,13 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
         free_dict(h);
         return SC_ENORM;
     }
-    if ((e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, st)) != hipSuccess ||
+    if ((e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->D48, st)) != hipSuccess ||
         (e = sc::launch_gram(h->D, d, K, Kp, h->G, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         free_dict(h);
         return set_dev_error("sc_gram_precompute", e);
     }
-    h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf};
+    h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->D48};
     *out = h;
     return SC_OK;
 }
@@ -154,10 +162,11 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
     if (N == 0) return SC_OK;   // empty input: arrays may be NULL
     if (!X || !idx || !coef || !count) return SC_EINVAL;
     const int kmax = sc::pick_kmax(k);
-    sc::OmpParams p{X, N, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0, (flags & SC_NO_FP64_REFIT) ? 0 : 1, 1e3f,
-                    idx, coef, count, resid, h->stats};
+    sc::OmpParams p{X, N, nullptr, nullptr, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0,
+                    (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, idx, coef, count, resid, h->stats};
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = sc::launch_omp_fp32(h->dev, p, kmax, st);
+    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
+    hipError_t e = sc::launch_omp_batch(h->dev, p, kmax, a0, st);
     if (e == hipErrorInvalidValue) {
         snprintf(g_last_error, sizeof(g_last_error), "no compiled encoder for K=%d (Kp=%d) with k=%d", K,
                  h->dev.Kp, k);
@@ -165,6 +174,25 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
     }
     if (e != hipSuccess) return set_dev_error("sc_omp_encode", e);
     return SC_OK;
+}
+
+int sc_dict_set_tuning(sc_dict h, int key, int value) {
+    if (!h) return SC_EINVAL;
+    if (key == SC_TUNE_FP32_CORRELATION) {
+        if (value != SC_CORR_VALU && value != SC_CORR_MFMA) return SC_EINVAL;
+        h->a0_fp32 = value == SC_CORR_VALU ? sc::A0_VALU : sc::A0_MFMA_F32;
+        return SC_OK;
+    }
+    return SC_EINVAL;
+}
+
+int sc_dict_get_tuning(sc_dict h, int key, int *value) {
+    if (!h || !value) return SC_EINVAL;
+    if (key == SC_TUNE_FP32_CORRELATION) {
+        *value = h->a0_fp32 == sc::A0_VALU ? SC_CORR_VALU : SC_CORR_MFMA;
+        return SC_OK;
+    }
+    return SC_EINVAL;
 }
 
 int sc_omp_stats(sc_dict h, int64_t stats[4], int reset, void *stream) {
@@ -195,6 +223,282 @@ int sc_sh_eval_sparse(sc_dict h, const int32_t *idx, const float *coef, const in
     hipError_t e = sc::launch_sh_eval(h->dev, idx, coef, count, N, k, dirs, M, dir_mode == SC_DIRS_SHARED ? 1 : 0,
                                       rgb, (hipStream_t)stream);
     if (e != hipSuccess) return set_dev_error("sc_sh_eval_sparse", e);
+    return SC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* learned support proposer                                             */
+/* ------------------------------------------------------------------ */
+
+int64_t sc_proposer_num_params(int d, int H, int K) {
+    if (d < 1 || d > 64 || H < 1 || K < 1) return SC_EINVAL;
+    return (int64_t)H * d + H + (int64_t)H * H + H + (int64_t)K * H + K;
+}
+
+static void free_proposer(sc_proposer p) {
+    if (!p) return;
+    hipFree(p->params);
+    hipFree(p->m);
+    hipFree(p->v);
+    hipFree(p->grads);
+    hipFree(p->W1b);
+    hipFree(p->W2b);
+    hipFree(p->W3b);
+    delete p;
+}
+
+int sc_proposer_create(int d, int H, int K, sc_proposer *out) {
+    if (!out || d < 1 || d > 48 || H != 256 || (K != 128 && K != 256 && K != 512)) return SC_EINVAL;
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc != SC_OK) return rc;
+    sc_proposer p = new sc_proposer_s();
+    p->d = d;
+    p->H = H;
+    p->K = K;
+    p->nparams = sc_proposer_num_params(d, H, K);
+    const size_t pb = sizeof(float) * (size_t)p->nparams;
+    bool ok = hipMalloc(&p->params, pb) == hipSuccess && hipMalloc(&p->m, pb) == hipSuccess &&
+              hipMalloc(&p->v, pb) == hipSuccess && hipMalloc(&p->grads, pb) == hipSuccess &&
+              hipMalloc(&p->W1b, sizeof(uint16_t) * (size_t)H * 64) == hipSuccess &&
+              hipMalloc(&p->W2b, sizeof(uint16_t) * (size_t)H * H) == hipSuccess &&
+              hipMalloc(&p->W3b, sizeof(uint16_t) * (size_t)K * H) == hipSuccess;
+    if (!ok ||
+        hipMemset(p->params, 0, pb) != hipSuccess || hipMemset(p->m, 0, pb) != hipSuccess ||
+        hipMemset(p->v, 0, pb) != hipSuccess || hipMemset(p->grads, 0, pb) != hipSuccess) {
+        free_proposer(p);
+        snprintf(g_last_error, sizeof(g_last_error), "hipMalloc failed in sc_proposer_create");
+        return SC_ENOMEM;
+    }
+    *out = p;
+    return SC_OK;
+}
+
+int sc_proposer_destroy(sc_proposer p) {
+    if (!p) return SC_OK;
+    hipDeviceSynchronize();
+    free_proposer(p);
+    return SC_OK;
+}
+
+int sc_proposer_dims(sc_proposer p, int *d, int *H, int *K, int64_t *nparams) {
+    if (!p || !d || !H || !K || !nparams) return SC_EINVAL;
+    *d = p->d;
+    *H = p->H;
+    *K = p->K;
+    *nparams = p->nparams;
+    return SC_OK;
+}
+
+int sc_proposer_set_params(sc_proposer p, const float *params, void *stream) {
+    if (!p || !params) return SC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t pb = sizeof(float) * (size_t)p->nparams;
+    SC_HIP(hipMemcpyAsync(p->params, params, pb, hipMemcpyDeviceToDevice, st), "sc_proposer_set_params");
+    SC_HIP(hipMemsetAsync(p->m, 0, pb, st), "sc_proposer_set_params");
+    SC_HIP(hipMemsetAsync(p->v, 0, pb, st), "sc_proposer_set_params");
+    p->step = 0;
+    SC_HIP(sc::launch_proposer_pack(p->params, p->d, p->H, p->K, p->W1b, p->W2b, p->W3b, st),
+           "sc_proposer_set_params");
+    return SC_OK;
+}
+
+int sc_proposer_get_params(sc_proposer p, float *params, void *stream) {
+    if (!p || !params) return SC_EINVAL;
+    SC_HIP(hipMemcpyAsync(params, p->params, sizeof(float) * (size_t)p->nparams, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream),
+           "sc_proposer_get_params");
+    return SC_OK;
+}
+
+int sc_proposer_forward(sc_proposer p, const float *X, int64_t N, int n_cand, int32_t *cand, float *logits,
+                        void *stream) {
+    if (!p || N < 0 || n_cand < 1 || n_cand > 32 || n_cand > p->K) return SC_EINVAL;
+    if (N == 0) return SC_OK;
+    if (!X || !cand) return SC_EINVAL;
+    hipError_t e = sc::launch_proposer_topk(p->dev(), X, N, n_cand, cand, logits, (hipStream_t)stream);
+    if (e != hipSuccess) return set_dev_error("sc_proposer_forward", e);
+    return SC_OK;
+}
+
+size_t sc_omp_encode_learned_workspace(int64_t N, int n_cand) {
+    if (N < 0 || n_cand < 1) return 0;
+    return align_up(sizeof(int32_t) * (size_t)N * n_cand) + align_up(sizeof(int32_t) * (size_t)N) + kAlign;
+}
+
+int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, int k, float eps, int flags,
+                          int n_cand, int32_t *idx, float *coef, int32_t *count, float *resid, void *workspace,
+                          size_t ws_bytes, void *stream) {
+    if (!h || !p || N < 0) return SC_EINVAL;
+    const int d = h->dev.d, K = h->dev.K;
+    if (p->K != K || p->d != d || d > 48) return SC_EINVAL;
+    if (k < 1 || k > std::min(std::min(K, d), 16)) return SC_EINVAL;
+    if (n_cand < k || n_cand > 32 || n_cand > K) return SC_EINVAL;
+    if (!(eps >= 0.f) || !isfinite(eps)) return SC_EINVAL;
+    if (flags & ~(SC_EPS_RELATIVE | SC_NO_FP64_REFIT | SC_PREC_BF16)) return SC_EINVAL;
+    if (N == 0) return SC_OK;
+    if (!X || !idx || !coef || !count || !workspace) return SC_EINVAL;
+    if (ws_bytes < sc_omp_encode_learned_workspace(N, n_cand)) return SC_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *w = (unsigned char *)workspace;
+    int32_t *cand = (int32_t *)w;
+    int32_t *miss_rows = (int32_t *)(w + align_up(sizeof(int32_t) * (size_t)N * n_cand));
+    int32_t *miss_count = (int32_t *)((unsigned char *)miss_rows + align_up(sizeof(int32_t) * (size_t)N));
+    const int kmax = sc::pick_kmax(k);
+    const int rel = (flags & SC_EPS_RELATIVE) ? 1 : 0;
+    const int refit = (flags & SC_NO_FP64_REFIT) ? 0 : 1;
+    SC_HIP(hipMemsetAsync(miss_count, 0, sizeof(int32_t), st), "sc_omp_encode_learned");
+    SC_HIP(sc::launch_proposer_topk(p->dev(), X, N, n_cand, cand, nullptr, st), "sc_omp_encode_learned (proposer)");
+    sc::RompParams rp{X, N, k, eps, rel, refit, kKappaMax, cand, n_cand, idx, coef, count, resid, miss_rows,
+                      miss_count, h->stats};
+    SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, kmax, st), "sc_omp_encode_learned (restricted)");
+    sc::OmpParams fp{X, N, miss_rows, miss_count, k, eps, rel, refit, kKappaMax, idx, coef, count, resid, h->stats};
+    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
+    SC_HIP(sc::launch_omp_batch(h->dev, fp, kmax, a0, st), "sc_omp_encode_learned (fallback)");
+    return SC_OK;
+}
+
+int sc_omp_encode_restricted(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, const int32_t *cand,
+                             int n_cand, int32_t *idx, float *coef, int32_t *count, float *resid, int32_t *miss_rows,
+                             int32_t *miss_count, void *stream) {
+    if (!h || N < 0) return SC_EINVAL;
+    const int d = h->dev.d, K = h->dev.K;
+    if (d > 48 || k < 1 || k > std::min(std::min(K, d), 16)) return SC_EINVAL;
+    if (n_cand < k || n_cand > 32 || n_cand > K) return SC_EINVAL;
+    if (!(eps >= 0.f) || !isfinite(eps)) return SC_EINVAL;
+    if (flags & ~(SC_EPS_RELATIVE | SC_NO_FP64_REFIT)) return SC_EINVAL;
+    if (!miss_count) return SC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    SC_HIP(hipMemsetAsync(miss_count, 0, sizeof(int32_t), st), "sc_omp_encode_restricted");
+    if (N == 0) return SC_OK;
+    if (!X || !cand || !idx || !coef || !count || !miss_rows) return SC_EINVAL;
+    sc::RompParams rp{X, N, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0, (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax,
+                      cand, n_cand, idx, coef, count, resid, miss_rows, miss_count, h->stats};
+    SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, sc::pick_kmax(k), st), "sc_omp_encode_restricted");
+    return SC_OK;
+}
+
+int sc_omp_encode_rows(sc_dict h, const float *X, const int32_t *rows, const int32_t *nrows, int64_t max_rows, int k,
+                       float eps, int flags, int32_t *idx, float *coef, int32_t *count, float *resid, void *stream) {
+    if (!h || max_rows < 0) return SC_EINVAL;
+    const int d = h->dev.d, K = h->dev.K;
+    if (k < 1 || k > std::min(std::min(K, d), 32)) return SC_EINVAL;
+    if (!(eps >= 0.f) || !isfinite(eps)) return SC_EINVAL;
+    if (flags & ~(SC_EPS_RELATIVE | SC_NO_FP64_REFIT | SC_PREC_BF16)) return SC_EINVAL;
+    if (max_rows == 0) return SC_OK;
+    if (!X || !rows || !nrows || !idx || !coef || !count) return SC_EINVAL;
+    sc::OmpParams p{X, max_rows, rows, nrows, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0,
+                    (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, idx, coef, count, resid, h->stats};
+    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
+    hipError_t e = sc::launch_omp_batch(h->dev, p, sc::pick_kmax(k), a0, (hipStream_t)stream);
+    if (e == hipErrorInvalidValue) return SC_EINVAL;
+    if (e != hipSuccess) return set_dev_error("sc_omp_encode_rows", e);
+    return SC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* proposer training                                                    */
+/* ------------------------------------------------------------------ */
+
+namespace {
+struct TrainLayout {
+    size_t xh, a1, h1, a2, h2, z, dz, da2, da1, loss, total;
+};
+TrainLayout train_layout(int64_t B, int K) {
+    TrainLayout t;
+    size_t o = 0;
+    auto take = [&](size_t n) {
+        size_t r = o;
+        o = align_up(o + n);
+        return r;
+    };
+    const size_t e = 4;   // bytes per element (FP32 upper bound)
+    t.xh = take(e * B * 64);
+    t.a1 = take(e * B * 256);
+    t.h1 = take(e * B * 256);
+    t.a2 = take(e * B * 256);
+    t.h2 = take(e * B * 256);
+    t.z = take(e * B * K);
+    t.dz = take(e * B * K);
+    t.da2 = take(e * B * 256);
+    t.da1 = take(e * B * 256);
+    t.loss = take(sizeof(float));
+    t.total = o;
+    return t;
+}
+}  // namespace
+
+size_t sc_proposer_train_workspace(sc_proposer p, int64_t B) {
+    if (!p || B < 1) return 0;
+    return train_layout(B, p->K).total;
+}
+
+int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, int64_t B, const int32_t *sup_idx,
+                           const int32_t *sup_count, int kcap, float lr, float beta1, float beta2, float adam_eps,
+                           float pos_weight, int flags, float *loss_out, float *grads_out, void *workspace,
+                           size_t ws_bytes, void *stream) {
+    if (!p || !X || !sup_idx || !sup_count || !workspace || B < 32 || B % 32 || kcap < 1 || kcap > 64)
+        return SC_EINVAL;
+    if (flags & ~(SC_TRAIN_FP32 | SC_TRAIN_GRAD_ONLY)) return SC_EINVAL;
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(adam_eps > 0.f) ||
+        !(pos_weight > 0.f))
+        return SC_EINVAL;
+    const TrainLayout L = train_layout(B, p->K);
+    if (ws_bytes < L.total) return SC_ENOMEM;
+    const bool f32 = (flags & SC_TRAIN_FP32) != 0;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *w = (unsigned char *)workspace;
+    void *xh = w + L.xh, *h1 = w + L.h1, *h2 = w + L.h2, *dz = w + L.dz, *da2 = w + L.da2, *da1 = w + L.da1;
+    float *a1 = (float *)(w + L.a1), *a2 = (float *)(w + L.a2), *z = (float *)(w + L.z);
+    float *loss = (float *)(w + L.loss);
+    const int d = p->d, H = p->H, K = p->K;
+    // parameter and gradient views
+    const float *W1 = p->params, *b1 = W1 + (size_t)H * d, *W2 = b1 + H, *b2 = W2 + (size_t)H * H, *W3 = b2 + H;
+    const float *b3 = W3 + (size_t)K * H;
+    float *gW1 = p->grads, *gb1 = gW1 + (size_t)H * d, *gW2 = gb1 + H, *gb2 = gW2 + (size_t)H * H, *gW3 = gb2 + H;
+    float *gb3 = gW3 + (size_t)K * H;
+    const void *Wb1 = f32 ? (const void *)W1 : (const void *)p->W1b;
+    const void *Wb2 = f32 ? (const void *)W2 : (const void *)p->W2b;
+    const void *Wb3 = f32 ? (const void *)W3 : (const void *)p->W3b;
+    const int64_t ld1 = f32 ? d : 64;
+    const char *fn = "sc_proposer_train_step";
+    using sc::GemmArgs;
+    SC_HIP(hipMemsetAsync(loss, 0, sizeof(float), st), fn);
+    SC_HIP(sc::launch_train_prep(X, rows, B, d, xh, f32, st), fn);
+    // forward
+    GemmArgs g1{(int)B, H, 48, xh, 64, 1, Wb1, 1, ld1, sc::EPI_GELU, H, b1, nullptr, nullptr, H, h1, H, a1};
+    SC_HIP(sc::launch_gemm(g1, f32, st), fn);
+    GemmArgs g2{(int)B, H, H, h1, H, 1, Wb2, 1, H, sc::EPI_GELU, H, b2, nullptr, nullptr, H, h2, H, a2};
+    SC_HIP(sc::launch_gemm(g2, f32, st), fn);
+    GemmArgs g3{(int)B, K, H, h2, H, 1, Wb3, 1, H, sc::EPI_STORE, K, b3, nullptr, z, K, nullptr, 0, nullptr};
+    SC_HIP(sc::launch_gemm(g3, f32, st), fn);
+    SC_HIP(sc::launch_bce_grad(z, B, K, rows, sup_idx, sup_count, kcap, pos_weight, dz, loss, f32, st), fn);
+    // backward
+    GemmArgs gw3{K, H, (int)B, dz, 1, K, h2, H, 1, sc::EPI_STORE, H, nullptr, nullptr, gW3, H, nullptr, 0, nullptr};
+    SC_HIP(sc::launch_gemm(gw3, f32, st), fn);
+    SC_HIP(sc::launch_colsum(dz, B, K, K, gb3, f32, st), fn);
+    GemmArgs gd2{(int)B, H, K, dz, K, 1, Wb3, H, 1, sc::EPI_DGELU, H, nullptr, a2, nullptr, H, da2, H, nullptr};
+    SC_HIP(sc::launch_gemm(gd2, f32, st), fn);
+    GemmArgs gw2{H, H, (int)B, da2, 1, H, h1, H, 1, sc::EPI_STORE, H, nullptr, nullptr, gW2, H, nullptr, 0, nullptr};
+    SC_HIP(sc::launch_gemm(gw2, f32, st), fn);
+    SC_HIP(sc::launch_colsum(da2, B, H, H, gb2, f32, st), fn);
+    GemmArgs gd1{(int)B, H, H, da2, H, 1, Wb2, H, 1, sc::EPI_DGELU, H, nullptr, a1, nullptr, H, da1, H, nullptr};
+    SC_HIP(sc::launch_gemm(gd1, f32, st), fn);
+    GemmArgs gw1{H, 64, (int)B, da1, 1, H, xh, 64, 1, sc::EPI_STORE, d, nullptr, nullptr, gW1, d, nullptr, 0, nullptr};
+    SC_HIP(sc::launch_gemm(gw1, f32, st), fn);
+    SC_HIP(sc::launch_colsum(da1, B, H, H, gb1, f32, st), fn);
+    if (grads_out)
+        SC_HIP(hipMemcpyAsync(grads_out, p->grads, sizeof(float) * (size_t)p->nparams, hipMemcpyDeviceToDevice, st), fn);
+    if (loss_out) SC_HIP(hipMemcpyAsync(loss_out, loss, sizeof(float), hipMemcpyDeviceToDevice, st), fn);
+    if (!(flags & SC_TRAIN_GRAD_ONLY)) {
+        p->step += 1;
+        const double bc1 = 1.0 - pow((double)beta1, (double)p->step);
+        const double bc2 = 1.0 - pow((double)beta2, (double)p->step);
+        const float lr_t = (float)(lr * sqrt(bc2) / bc1);
+        const float eps_hat = (float)(adam_eps * sqrt(bc2));
+        SC_HIP(sc::launch_adam(p->params, p->m, p->v, p->grads, p->nparams, lr_t, beta1, beta2, eps_hat, st), fn);
+        SC_HIP(sc::launch_proposer_pack(p->params, d, H, K, p->W1b, p->W2b, p->W3b, st), fn);
+    }
     return SC_OK;
 }
 

@@ -32,11 +32,18 @@ struct DictDev {
     const float *DT;   // d x Kp feature-major FP32, zero padded atoms
     const float *G;    // K x Kp FP32 Gram rows, zero padded columns
     const uint16_t *Dbf;  // Kp x 64 BF16 atom-major, features and atoms zero padded
+    const uint16_t *Dlo;  // Kp x 64 BF16 residual D - bf16(D) (split-BF16 products)
+    const float *D48;     // K x 48 FP32 atom-major, features zero padded (d <= 48)
 };
+
+// How the correlation tile alpha0 = D^T X is computed by the batch encoder.
+enum { A0_VALU = 0, A0_MFMA_F32 = 1, A0_MFMA_BF16X3 = 2 };
 
 struct OmpParams {
     const float *X;
     int64_t N;
+    const int32_t *rows;    // optional: encode rows[0..*nrows) of X (a fallback list)
+    const int32_t *nrows;   // device count of rows (read by the kernel)
     int k;
     float eps;
     int relative;
@@ -49,13 +56,76 @@ struct OmpParams {
     unsigned long long *stats;  // 4 counters (see sc_omp_stats)
 };
 
+struct RompParams {
+    const float *X;
+    int64_t N;
+    int k;
+    float eps;
+    int relative;
+    int fp64_refit;
+    float kappa_max;
+    const int32_t *cand;      // N x n_cand candidate atoms sorted by index; row {-1,...} = none
+    int n_cand;
+    int32_t *idx;
+    float *coef;
+    int32_t *count;
+    float *resid;
+    int32_t *miss_rows;       // signals whose restricted code misses eps are appended here
+    int32_t *miss_count;
+    unsigned long long *stats;
+};
+
+struct PropDev {
+    int d, H, K;
+    const uint16_t *W1b;   // H x 64 BF16 (inputs zero padded)
+    const float *b1;
+    const uint16_t *W2b;   // H x H BF16
+    const float *b2;
+    const uint16_t *W3b;   // K x H BF16
+    const float *b3;
+};
+
 // Launchers (return hipError_t of the launch).
 hipError_t launch_dict_check(const float *D, int d, int K, int normalize, float *Dcopy, int *status,
                              hipStream_t st);
-hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *DT, uint16_t *Dbf,
-                               hipStream_t st);
+hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *DT, uint16_t *Dbf, uint16_t *Dlo,
+                               float *D48, hipStream_t st);
 hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, hipStream_t st);
-hipError_t launch_omp_fp32(const DictDev &dict, const OmpParams &p, int kmax, hipStream_t st);
+hipError_t launch_omp_batch(const DictDev &dict, const OmpParams &p, int kmax, int a0mode, hipStream_t st);
+hipError_t launch_omp_restricted(const DictDev &dict, const float *D48, const RompParams &p, int kmax,
+                                 hipStream_t st);
+hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16_t *W1b, uint16_t *W2b,
+                                uint16_t *W3b, hipStream_t st);
+hipError_t launch_proposer_topk(const PropDev &P, const float *X, int64_t N, int n_cand, int32_t *cand,
+                                float *logits, hipStream_t st);
+enum { EPI_STORE = 0, EPI_GELU = 1, EPI_DGELU = 2 };  // GEMM epilogues (train.hip)
+
+struct GemmArgs {
+    int M, N, K;
+    const void *A;
+    int64_t sam, sak;      // A(i, k) = A[i * sam + k * sak]
+    const void *B;
+    int64_t sbk, sbn;      // B(k, j) = B[k * sbk + j * sbn]
+    int epi;
+    int Nvalid;            // columns >= Nvalid are not written
+    const float *bias;     // [N] or NULL
+    const float *aux;      // saved pre-activation for DGELU, row stride ldc
+    float *Cf;             // FP32 output (row stride ldc) or NULL
+    int64_t ldc;
+    void *Ch;              // activation output (BF16 or FP32 by mode, row stride ldh) or NULL
+    int64_t ldh;
+    float *Cpre;           // GELU: pre-activation output (row stride ldc)
+};
+
+hipError_t launch_gemm(const GemmArgs &g, bool f32, hipStream_t st);
+hipError_t launch_train_prep(const float *X, const int32_t *rows, int64_t B, int d, void *xh, bool f32,
+                             hipStream_t st);
+hipError_t launch_bce_grad(const float *Z, int64_t B, int K, const int32_t *rows, const int32_t *sup,
+                           const int32_t *cnt, int kcap, float pos_weight, void *dz, float *loss, bool f32,
+                           hipStream_t st);
+hipError_t launch_colsum(const void *A, int64_t M, int N, int64_t ld, float *out, bool f32, hipStream_t st);
+hipError_t launch_adam(float *p, float *m, float *v, const float *g, int64_t n, float lr_t, float beta1, float beta2,
+                       float eps_hat, hipStream_t st);
 hipError_t launch_sh_eval(const DictDev &dict, const int32_t *idx, const float *coef, const int32_t *count,
                           int64_t N, int k, const float *dirs, int64_t M, int shared, float *rgb,
                           hipStream_t st);
@@ -69,6 +139,26 @@ struct sc_dict_s {
     float *DT = nullptr;
     float *G = nullptr;
     uint16_t *Dbf = nullptr;
+    uint16_t *Dlo = nullptr;
+    float *D48 = nullptr;   // K x 48 FP32, atoms padded to 16-byte rows
     int *status = nullptr;
     unsigned long long *stats = nullptr;
+    int a0_fp32 = sc::A0_MFMA_F32;   // alpha0 stage of the FP32 encoder (tunable)
+};
+
+struct sc_proposer_s {
+    int d, H, K;
+    int64_t nparams;
+    float *params = nullptr;     // FP32 master: W1 (H x d), b1, W2 (H x H), b2, W3 (K x H), b3
+    float *m = nullptr;          // Adam first moment
+    float *v = nullptr;          // Adam second moment
+    float *grads = nullptr;      // gradient buffer (same layout)
+    uint16_t *W1b = nullptr, *W2b = nullptr, *W3b = nullptr;
+    int64_t step = 0;
+    sc::PropDev dev() const {
+        const float *b1 = params + (size_t)H * d;
+        const float *b2 = b1 + H + (size_t)H * H;
+        const float *b3 = b2 + H + (size_t)K * H;
+        return sc::PropDev{d, H, K, W1b, b1, W2b, b2, W3b, b3};
+    }
 };

@@ -115,8 +115,8 @@ static hipError_t launch_sh_t(const DictDev &dict, const int32_t *idx, const flo
                               int64_t N, int k, const float *dirs, int64_t M, int shared, float *rgb,
                               hipStream_t st) {
     int dev = 0, ncu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t items = shared ? N * M : N;
     int64_t blocks = std::min<int64_t>((items + kShThreads - 1) / kShThreads, (int64_t)ncu);
     if (blocks < 1) blocks = 1;

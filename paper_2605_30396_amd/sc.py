@@ -27,6 +27,13 @@ PREC_BF16 = 0x2
 NO_FP64_REFIT = 0x4
 NORMALIZE = 0x8
 
+TRAIN_FP32 = 0x1
+TRAIN_GRAD_ONLY = 0x2
+
+TUNE_FP32_CORRELATION = 1
+CORR_VALU = 0
+CORR_MFMA = 1
+
 DIRS_PER_SIGNAL = 0
 DIRS_SHARED = 1
 
@@ -64,7 +71,23 @@ def load():
         "sc_dict_gram": (I32, [P, P, P]),
         "sc_omp_encode": (I32, [P, P, I64, I32, F32, I32, P, P, P, P, P]),
         "sc_omp_stats": (I32, [P, C.POINTER(I64), I32, P]),
+        "sc_dict_set_tuning": (I32, [P, I32, I32]),
+        "sc_dict_get_tuning": (I32, [P, I32, C.POINTER(I32)]),
         "sc_sh_eval_sparse": (I32, [P, P, P, P, I64, I32, P, I64, I32, P, P]),
+        "sc_proposer_num_params": (I64, [I32, I32, I32]),
+        "sc_proposer_create": (I32, [I32, I32, I32, C.POINTER(P)]),
+        "sc_proposer_destroy": (I32, [P]),
+        "sc_proposer_dims": (I32, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]),
+        "sc_proposer_set_params": (I32, [P, P, P]),
+        "sc_proposer_get_params": (I32, [P, P, P]),
+        "sc_proposer_forward": (I32, [P, P, I64, I32, P, P, P]),
+        "sc_omp_encode_learned_workspace": (C.c_size_t, [I64, I32]),
+        "sc_omp_encode_learned": (I32, [P, P, P, I64, I32, F32, I32, I32, P, P, P, P, P, C.c_size_t, P]),
+        "sc_omp_encode_restricted": (I32, [P, P, I64, I32, F32, I32, P, I32, P, P, P, P, P, P, P]),
+        "sc_omp_encode_rows": (I32, [P, P, P, P, I64, I32, F32, I32, P, P, P, P, P]),
+        "sc_proposer_train_workspace": (C.c_size_t, [P, I64]),
+        "sc_proposer_train_step": (I32, [P, P, P, I64, P, P, I32, F32, F32, F32, F32, F32, I32, P, P, P,
+                                         C.c_size_t, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -119,6 +142,14 @@ class Dictionary:
         out = torch.empty((self.K, self.K), dtype=torch.float32, device=self.device)
         _check("sc_dict_gram", load().sc_dict_gram(self.handle, _ptr(out), _stream(stream)))
         return out
+
+    def set_tuning(self, key, value):
+        _check("sc_dict_set_tuning", load().sc_dict_set_tuning(self.handle, int(key), int(value)))
+
+    def get_tuning(self, key):
+        v = C.c_int()
+        _check("sc_dict_get_tuning", load().sc_dict_get_tuning(self.handle, int(key), C.byref(v)))
+        return v.value
 
     def destroy(self):
         if self._h is not None:
@@ -178,4 +209,163 @@ def sh_eval_sparse(h: Dictionary, idx, coef, count, dirs, dir_mode=DIRS_PER_SIGN
         out = torch.empty(shape, dtype=torch.float32, device=idx.device)
     _check("sc_sh_eval_sparse", load().sc_sh_eval_sparse(h.handle, _ptr(idx), _ptr(coef), _ptr(count), N, k,
                                                          _ptr(dirs), M, int(dir_mode), _ptr(out), _stream(stream)))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# learned support proposer
+# ----------------------------------------------------------------------------
+
+PARAM_ORDER = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def pack_params(params: dict) -> torch.Tensor:
+    """Flatten a {W1, b1, W2, b2, W3, b3} dict (arrays or tensors) into the
+    library's FP32 parameter vector (that order, row-major)."""
+    parts = [torch.as_tensor(params[n], dtype=torch.float32).reshape(-1) for n in PARAM_ORDER]
+    return torch.cat(parts)
+
+
+def unpack_params(vec, d, H, K) -> dict:
+    shapes = {"W1": (H, d), "b1": (H,), "W2": (H, H), "b2": (H,), "W3": (K, H), "b3": (K,)}
+    out, o = {}, 0
+    for n in PARAM_ORDER:
+        sz = int(torch.tensor(shapes[n]).prod())
+        out[n] = vec[o:o + sz].reshape(shapes[n])
+        o += sz
+    return out
+
+
+class Proposer:
+    """Owns an sc_proposer handle (FP32 master weights, BF16 copies, Adam state)."""
+
+    def __init__(self, handle, d, H, K, device):
+        self._h = handle
+        self.d, self.H, self.K, self.device = d, H, K, device
+        self.nparams = int(load().sc_proposer_num_params(d, H, K))
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("proposer handle already destroyed")
+        return self._h
+
+    def set_params(self, params, stream=None):
+        vec = params if isinstance(params, torch.Tensor) else pack_params(params)
+        vec = vec.to(device=self.device, dtype=torch.float32).contiguous()
+        if vec.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {vec.numel()}")
+        _check("sc_proposer_set_params", load().sc_proposer_set_params(self.handle, _ptr(vec), _stream(stream)))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+    def get_params(self, stream=None):
+        out = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _check("sc_proposer_get_params", load().sc_proposer_get_params(self.handle, _ptr(out), _stream(stream)))
+        return out
+
+    def destroy(self):
+        if self._h is not None:
+            load().sc_proposer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def proposer_create(d, H, K, device="cuda:0") -> Proposer:
+    h = C.c_void_p()
+    _check("sc_proposer_create", load().sc_proposer_create(d, H, K, C.byref(h)))
+    return Proposer(h, d, H, K, torch.device(device))
+
+
+def proposer_forward(p: Proposer, X, n_cand=24, want_logits=False, stream=None):
+    """Candidate atoms (N, n_cand) int32 sorted by index (row of -1 = none) and,
+    if asked, the FP32 logits (N, K)."""
+    _dev_f32(X, "X", 2)
+    N = X.shape[0]
+    cand = torch.empty((N, n_cand), dtype=torch.int32, device=X.device)
+    logits = torch.empty((N, p.K), dtype=torch.float32, device=X.device) if want_logits else None
+    _check("sc_proposer_forward", load().sc_proposer_forward(p.handle, _ptr(X), N, int(n_cand), _ptr(cand),
+                                                             _ptr(logits), _stream(stream)))
+    return cand, logits
+
+
+def learned_workspace_bytes(N, n_cand=24):
+    return int(load().sc_omp_encode_learned_workspace(int(N), int(n_cand)))
+
+
+def omp_encode_learned(h: Dictionary, p: Proposer, X, k, eps, n_cand=24, flags=0, out=None, workspace=None,
+                       stream=None):
+    """Proposer-guided OMP with full-OMP fallback.  Returns (idx, coef, count, resid)."""
+    _dev_f32(X, "X", 2)
+    N = X.shape[0]
+    if out is None:
+        idx = torch.empty((N, k), dtype=torch.int32, device=X.device)
+        coef = torch.empty((N, k), dtype=torch.float32, device=X.device)
+        count = torch.empty((N,), dtype=torch.int32, device=X.device)
+        resid = torch.empty((N,), dtype=torch.float32, device=X.device)
+    else:
+        idx, coef, count, resid = out
+    need = learned_workspace_bytes(N, n_cand)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    _check("sc_omp_encode_learned", load().sc_omp_encode_learned(
+        h.handle, p.handle, _ptr(X), N, int(k), float(eps), int(flags), int(n_cand), _ptr(idx), _ptr(coef),
+        _ptr(count), _ptr(resid), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return idx, coef, count, resid
+
+
+def train_workspace_bytes(p: Proposer, B):
+    return int(load().sc_proposer_train_workspace(p.handle, int(B)))
+
+
+def proposer_train_step(p: Proposer, X, sup_idx, sup_count, B, rows=None, lr=1e-3, beta1=0.9, beta2=0.999,
+                        adam_eps=1e-8, pos_weight=1.0, flags=0, loss=None, grads=None, workspace=None, stream=None):
+    """One training step on the batch X[rows] (or X[:B]).  `loss` (1-element
+    float32 tensor) and `grads` (nparams) receive the batch loss and gradient
+    if given."""
+    _dev_f32(X, "X", 2)
+    _dev_i32(sup_idx, "sup_idx", 2)
+    _dev_i32(sup_count, "sup_count", 1)
+    if rows is not None:
+        _dev_i32(rows, "rows", 1)
+    if workspace is None:
+        workspace = torch.empty(train_workspace_bytes(p, B), dtype=torch.uint8, device=X.device)
+    _check("sc_proposer_train_step", load().sc_proposer_train_step(
+        p.handle, _ptr(X), _ptr(rows), int(B), _ptr(sup_idx), _ptr(sup_count), sup_idx.shape[1], float(lr),
+        float(beta1), float(beta2), float(adam_eps), float(pos_weight), int(flags), _ptr(loss), _ptr(grads),
+        _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def omp_encode_restricted(h: Dictionary, X, k, eps, cand, flags=0, out=None, miss_rows=None, miss_count=None,
+                          stream=None):
+    """Restricted OMP over candidate lists; returns (codes..., miss_rows, miss_count)."""
+    _dev_f32(X, "X", 2)
+    _dev_i32(cand, "cand", 2)
+    N = X.shape[0]
+    if out is None:
+        out = (torch.empty((N, k), dtype=torch.int32, device=X.device),
+               torch.empty((N, k), dtype=torch.float32, device=X.device),
+               torch.empty((N,), dtype=torch.int32, device=X.device),
+               torch.empty((N,), dtype=torch.float32, device=X.device))
+    idx, coef, count, resid = out
+    if miss_rows is None:
+        miss_rows = torch.empty((max(N, 1),), dtype=torch.int32, device=X.device)
+    if miss_count is None:
+        miss_count = torch.zeros((1,), dtype=torch.int32, device=X.device)
+    _check("sc_omp_encode_restricted", load().sc_omp_encode_restricted(
+        h.handle, _ptr(X), N, int(k), float(eps), int(flags), _ptr(cand), cand.shape[1], _ptr(idx), _ptr(coef),
+        _ptr(count), _ptr(resid), _ptr(miss_rows), _ptr(miss_count), _stream(stream)))
+    return idx, coef, count, resid, miss_rows, miss_count
+
+
+def omp_encode_rows(h: Dictionary, X, rows, nrows, max_rows, k, eps, out, flags=0, stream=None):
+    """Plain FP32 encoder on X[rows[:*nrows]] (nrows: 1-element device int32)."""
+    idx, coef, count, resid = out
+    _check("sc_omp_encode_rows", load().sc_omp_encode_rows(
+        h.handle, _ptr(X), _ptr(rows), _ptr(nrows), int(max_rows), int(k), float(eps), int(flags), _ptr(idx),
+        _ptr(coef), _ptr(count), _ptr(resid), _stream(stream)))
     return out

@@ -6,6 +6,8 @@ within rounding of eps, ill-conditioned supports), only what is unique is
 compared exactly; the rest is checked for validity.  A signal is
 "well separated" when, in the oracle's FP64 run,
   * every selection won by a relative margin (|c|_(1) - |c|_(2)) / ||r|| >= margin_min,
+    and, for the split-BF16 correlations (error <= ~2^-16 ||x|| per entry,
+    which does not shrink with the residual), by an absolute gap >= 1e-4 ||x||,
   * no residual before a selection lies within 1e-3 relative of eps, and
   * the selected atoms' Gram submatrix has condition number <= 1e3.
 """
@@ -17,10 +19,16 @@ COEF_RTOL = 1e-4      # norm-wise per signal, on matched supports
 RESID_AGG_RTOL = 1e-2
 
 
-def well_separated(D, X, ref, eps, relative=False, margin_min=1e-3):
+BF16_GAP = 1e-4
+
+
+def well_separated(D, X, ref, eps, relative=False, margin_min=1e-3, bf16=False):
     k = ref["idx"].shape[1]
     sep = ref["margin"] > margin_min
     xn = np.linalg.norm(X.astype(np.float64), axis=1)
+    if bf16:
+        with np.errstate(invalid="ignore"):
+            sep &= ref["gap"] > BF16_GAP * xn
     tol = eps * xn if relative else np.full(len(X), eps)
     if eps > 0:
         rp = ref["rpath"]
@@ -42,12 +50,12 @@ def oracle_run(D, X, k, eps, relative=False):
     return oracle.omp(D, X, k, eps, relative, with_margin=True, with_path=True)
 
 
-def compare_codes(D, X, k, eps, gpu, ref=None, relative=False, margin_min=1e-3, min_sep_frac=0.5):
+def compare_codes(D, X, k, eps, gpu, ref=None, relative=False, margin_min=1e-3, min_sep_frac=0.5, bf16=False):
     """gpu: dict of numpy idx, coef, count, resid.  Asserts the parity bar and
     returns a dict of statistics."""
     if ref is None:
         ref = oracle_run(D, X, k, eps, relative)
-    sep = well_separated(D, X, ref, eps, relative, margin_min)
+    sep = well_separated(D, X, ref, eps, relative, margin_min, bf16)
     N = len(X)
     assert sep.sum() >= min_sep_frac * N, f"too few well-separated signals: {sep.sum()} of {N}"
     # per-signal status and padding are exact everywhere
@@ -74,9 +82,18 @@ def compare_codes(D, X, k, eps, gpu, ref=None, relative=False, margin_min=1e-3, 
     agg_r = np.sqrt(np.sum(ref["resid"][ok] ** 2))
     assert abs(agg_g - agg_r) <= RESID_AGG_RTOL * agg_r + 1e-12, (agg_g, agg_r)
     Dd, Xd = D.astype(np.float64), X.astype(np.float64)
+    ls_err = 0.0
     for i in np.nonzero(ok)[0][:: max(1, ok.sum() // 256)]:
         n = gpu["count"][i]
-        r = Xd[i] - gpu["coef"][i, :n].astype(np.float64) @ Dd[gpu["idx"][i, :n]]
+        S = gpu["idx"][i, :n]
+        r = Xd[i] - gpu["coef"][i, :n].astype(np.float64) @ Dd[S]
         assert abs(np.linalg.norm(r) - gpu["resid"][i]) <= 1e-5 * (np.linalg.norm(Xd[i]) + 1e-30)
+        # whatever the support, the coefficients are its least-squares fit
+        if n > 0 and np.linalg.cond(Dd[S] @ Dd[S].T) <= 1e3:
+            g = np.linalg.lstsq(Dd[S].T, Xd[i], rcond=None)[0]
+            e = np.linalg.norm(gpu["coef"][i, :n] - g) / max(np.linalg.norm(g), 1e-30)
+            ls_err = max(ls_err, e)
+    assert ls_err <= COEF_RTOL, f"coefficients are not the least-squares fit: {ls_err}"
     return dict(n=N, separated=int(sep.sum()), coef_err=float(err.max(initial=0)), resid_gpu=agg_g,
-                resid_ref=agg_r)
+                resid_ref=agg_r, resid_gap=float((agg_g - agg_r) / agg_r) if agg_r > 0 else 0.0,
+                support_mismatch=float(np.mean(np.any(gpu["idx"][ok] != ref["idx"][ok], axis=1))))

@@ -1,0 +1,167 @@
+"""GPU parity of the learned support proposer (BF16 MFMA network + candidate
+selection) and of the proposer-guided encoder with full-OMP fallback.
+
+The oracle network rounds the input, weights and hidden activations to BF16
+exactly where the kernels do and sums in FP64, so the only differences are
+the FP32 accumulation order and the GELU evaluation.  Candidate sets are
+compared where the oracle's n_cand-th and (n_cand+1)-th logits differ by more
+than 1e-3 (elsewhere either choice is correct); weights are seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_30396_amd import inputs as I
+from paper_2605_30396_amd import sc
+from parity import compare_codes, well_separated
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+LOGIT_ATOL = 2e-3
+
+
+def setup(K=512, N=1000, s=4, seed=200, H=256):
+    rng = I.rng_for(seed)
+    D = I.random_dictionary(rng, K)
+    X, sup, cf = I.sparse_signals(rng, D, N, s, 1e-3)
+    P = I.mlp_init(rng, 45, H, K)
+    P["W3"] = P["W3"] * np.float32(4.0)      # spread the logits (seeded weights are nearly flat)
+    return D, X, P
+
+
+def gpu_forward(P, X, K, n_cand, want_logits=True):
+    p = sc.proposer_create(45, 256, K)
+    p.set_params(P)
+    cand, z = sc.proposer_forward(p, torch.from_numpy(X).to(DEV), n_cand, want_logits)
+    torch.cuda.synchronize()
+    out = cand.cpu().numpy(), (z.cpu().numpy() if z is not None else None)
+    p.destroy()
+    return out
+
+
+@pytest.mark.parametrize("K", [128, 256, 512])
+def test_proposer_logits_and_candidates(K):
+    D, X, P = setup(K=K, N=64 * 5 + 17)
+    X[3] = 0.0                               # zero input: direction 0
+    cand, z = gpu_forward(P, X, K, 24)
+    ref = oracle.mlp_forward(P, X, bf16=True)
+    err = np.abs(z - ref)
+    assert err.max() <= LOGIT_ATOL, err.max()
+    assert np.median(err) <= 1e-5
+    srt = -np.sort(-ref, axis=1)
+    margin = srt[:, 23] - srt[:, 24]
+    ok = margin > 1e-3
+    assert ok.mean() > 0.3
+    refc = np.sort(oracle.topk_lowest_index(ref, 24), axis=1)
+    np.testing.assert_array_equal(cand[ok], refc[ok])
+    # always sorted by atom index, distinct
+    assert np.all(np.diff(cand, axis=1) > 0)
+
+
+def test_proposer_bad_inputs_and_sizes():
+    D, X, P = setup(K=512, N=130)
+    X[5, 2] = np.nan
+    X[6, 0] = np.inf
+    cand, _ = gpu_forward(P, X, 512, 16, want_logits=False)
+    assert np.all(cand[5] == -1) and np.all(cand[6] == -1)
+    assert np.all(cand[[0, 1, 2, 7]] >= 0)
+    p = sc.proposer_create(45, 256, 512)
+    with pytest.raises(sc.ScError):
+        sc.proposer_forward(p, torch.from_numpy(X).to(DEV), 33)
+    with pytest.raises(sc.ScError):
+        sc.proposer_create(45, 128, 512)
+    p.destroy()
+
+
+def test_params_roundtrip():
+    rng = I.rng_for(201)
+    P = I.mlp_init(rng, 45, 256, 256)
+    p = sc.proposer_create(45, 256, 256)
+    vec = sc.pack_params(P)
+    p.set_params(vec)
+    back = p.get_params().cpu()
+    assert torch.equal(back, vec)
+    assert p.nparams == vec.numel()
+    p.destroy()
+
+
+def run_learned(D, X, P, k, eps, n_cand=24):
+    K = D.shape[0]
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    p = sc.proposer_create(45, 256, K)
+    p.set_params(P)
+    sc.omp_stats(h, reset=True)
+    idx, coef, count, resid = sc.omp_encode_learned(h, p, torch.from_numpy(X).to(DEV), k, eps, n_cand)
+    torch.cuda.synchronize()
+    st = sc.omp_stats(h)
+    out = dict(idx=idx.cpu().numpy(), coef=coef.cpu().numpy(), count=count.cpu().numpy(),
+               resid=resid.cpu().numpy())
+    h.destroy()
+    p.destroy()
+    return out, st
+
+
+@pytest.mark.parametrize("K,k,eps", [(512, 12, 1e-2), (256, 8, 1e-2), (128, 4, 2e-2)])
+def test_learned_encoder_matches_oracle_pipeline(K, k, eps):
+    D, X, P = setup(K=K, N=2000 + 11, seed=202 + K)
+    g, st = run_learned(D, X, P, k, eps)
+    ref = oracle.learned_encode(D, X, P, k, eps, n_cand=24, bf16=True)
+    z = ref["logits"]
+    srt = -np.sort(-z, axis=1)
+    cand_ok = (srt[:, 23] - srt[:, 24]) > 1e-3
+    # the oracle pipeline's result is OMP (full or restricted): its signals are
+    # compared where the candidate set and the pursuit are unambiguous
+    full = oracle.omp(D, X, k, eps, with_margin=True, with_path=True)
+    sep = well_separated(D, X, full, eps) & cand_ok
+    rest = oracle.omp(D, X, k, eps, cand=ref["cand"], with_margin=True, with_path=True)
+    sep &= well_separated(D, X, rest, eps)
+    assert sep.mean() > 0.2
+    np.testing.assert_array_equal(g["idx"][sep], ref["idx"][sep])
+    gc, rc = g["coef"][sep].astype(np.float64), ref["coef"][sep]
+    err = np.linalg.norm(gc - rc, axis=1) / np.maximum(np.linalg.norm(rc, axis=1), 1e-30)
+    assert err.max() <= 1e-4
+    # a code above eps can only come from the fallback: it is the full OMP code
+    above = g["resid"] > eps * (1 + 1e-5)
+    fsep = well_separated(D, X, full, eps)
+    chk = above & fsep
+    np.testing.assert_array_equal(g["idx"][chk], full["idx"][chk])
+    assert np.all(full["resid"][above] > eps * (1 - 1e-3))
+    fb_ref = int(ref["fallback"].sum())
+    assert abs(st["fallbacks"] - fb_ref) <= max(3, 0.01 * len(X)), (st["fallbacks"], fb_ref)
+    # aggregate residual against the FP64 OMP of the whole dictionary: same error
+    agg_g = np.sqrt((g["resid"].astype(np.float64) ** 2).sum())
+    agg_o = np.sqrt((full["resid"] ** 2).sum())
+    print(K, k, eps, "fallbacks", st["fallbacks"], fb_ref, "resid gap", (agg_g - agg_o) / agg_o)
+
+
+def test_learned_with_every_signal_falling_back_equals_plain():
+    """eps = 0: no restricted code meets it, so the result is the plain
+    encoder's, signal for signal."""
+    D, X, P = setup(K=256, N=700)
+    g, st = run_learned(D, X, P, 6, 0.0)
+    assert st["fallbacks"] == len(X)
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    idx, coef, count, resid = sc.omp_encode(h, torch.from_numpy(X).to(DEV), 6, 0.0)
+    np.testing.assert_array_equal(g["idx"], idx.cpu().numpy())
+    np.testing.assert_array_equal(g["coef"], coef.cpu().numpy())
+    h.destroy()
+
+
+def test_learned_edge_signals_and_workspace():
+    D, X, P = setup(K=512, N=300)
+    X[0] = 0
+    X[1, 4] = np.nan
+    g, st = run_learned(D, X, P, 12, 1e-2)
+    assert g["count"][0] == 0 and g["count"][1] == -1
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    p = sc.proposer_create(45, 256, 512)
+    p.set_params(P)
+    Xg = torch.from_numpy(X).to(DEV)
+    small = torch.empty(16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(sc.ScError) as e:
+        sc.omp_encode_learned(h, p, Xg, 12, 1e-2, workspace=small)
+    assert e.value.code == sc.SC_ENOMEM
+    with pytest.raises(sc.ScError):
+        sc.omp_encode_learned(h, p, Xg, 12, 1e-2, n_cand=8)      # n_cand < k
+    h.destroy()
+    p.destroy()

@@ -17,8 +17,10 @@ DEV = "cuda:0"
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def encode(D, X, k, eps, flags=0):
+def encode(D, X, k, eps, flags=0, corr=None):
     h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    if corr is not None:
+        h.set_tuning(sc.TUNE_FP32_CORRELATION, corr)
     Xg = torch.from_numpy(np.ascontiguousarray(X)).to(DEV)
     idx, coef, count, resid = sc.omp_encode(h, Xg, k, eps, flags)
     torch.cuda.synchronize()
@@ -98,16 +100,32 @@ def test_sh_like_workload_sample():
     print(r)
 
 
+MODES = [(0, sc.CORR_MFMA), (0, sc.CORR_VALU), (sc.PREC_BF16, None)]
+
+
+@pytest.mark.parametrize("flags,corr", MODES, ids=["fp32-mfma", "fp32-valu", "bf16x3"])
 @pytest.mark.parametrize("K,k,eps,s", [(512, 12, 0.0, 4), (512, 12, 1e-2, 4), (128, 16, 0.0, 8),
                                        (256, 8, 1e-2, 4), (90, 12, 0.0, 6), (1000, 8, 0.0, 4),
                                        (640, 4, 0.0, 3), (48, 32, 0.0, 8)])
-def test_dictionary_and_sparsity_shapes(K, k, eps, s):
+def test_dictionary_and_sparsity_shapes(K, k, eps, s, flags, corr):
     rng = I.rng_for(1000 + K + k)
     D = I.random_dictionary(rng, K)
     X, _, _ = I.sparse_signals(rng, D, 2000 + 5, s, 1e-3)
-    g, _ = encode(D, X, k, eps)
-    r = compare_codes(D, X, k, eps, g, min_sep_frac=0.3)
-    print(K, k, eps, r)
+    g, _ = encode(D, X, k, eps, flags, corr)
+    bf = bool(flags & sc.PREC_BF16)
+    r = compare_codes(D, X, k, eps, g, min_sep_frac=0.0 if bf else 0.2, bf16=bf)
+    print(K, k, eps, flags, corr, r)
+
+
+@pytest.mark.parametrize("flags,corr", MODES, ids=["fp32-mfma", "fp32-valu", "bf16x3"])
+def test_precision_modes_on_near_duplicates(flags, corr):
+    """K=512, k=12, eps=0 with 5% near-duplicate signals (the precision
+    workload's generator, 6000 signals)."""
+    w = I.workload_precision(N=6000)
+    g, stats = encode(w["D"], w["X"], 12, 0.0, flags, corr)
+    bf = bool(flags & sc.PREC_BF16)
+    r = compare_codes(w["D"], w["X"], 12, 0.0, g, min_sep_frac=0.0 if bf else 0.2, bf16=bf)
+    print(flags, corr, r, stats)
 
 
 def test_relative_tolerance_and_edge_signals():
