@@ -140,10 +140,14 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
  * Tuning of a dictionary handle (chosen by the autotuner; results do not
  * depend on it beyond FP32 rounding order):
  *   SC_TUNE_FP32_CORRELATION  how the FP32 encoder computes alpha0 = D^T x for
- *     a tile of 16 signals: SC_CORR_MFMA (FP32 matrix cores, default) or
- *     SC_CORR_VALU (FP32 FMAs).
+ *     a tile of 16 signals: SC_CORR_VALU (FP32 FMAs, default) or SC_CORR_MFMA
+ *     (FP32 matrix cores).
+ *   SC_TUNE_ROW_CACHE  Gram rows of the first selected atoms kept in
+ *     registers by the encoder: 0 (every row re-read from cache memory when
+ *     the correlations are formed) or 4 (default; applies to K <= 512).
  */
 #define SC_TUNE_FP32_CORRELATION 1
+#define SC_TUNE_ROW_CACHE 2
 #define SC_CORR_VALU 0
 #define SC_CORR_MFMA 1
 int sc_dict_set_tuning(sc_dict h, int key, int value);
@@ -313,6 +317,86 @@ int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, i
                            const int32_t *sup_count, int kcap, float lr, float beta1, float beta2, float adam_eps,
                            float pos_weight, int flags, float *loss_out, float *grads_out, void *workspace,
                            size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Many scenes in one launch                                            */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Compression is applied per trained scene (Sec. 3: each scene has its own
+ * learned dictionary), so a batch of scenes of uneven size, each with its
+ * own dictionary D_s, sparsity cap k_s and tolerance eps_s, is encoded by one
+ * persistent launch: every scene's codes are those sc_omp_encode(D_s, X_s,
+ * k_s, eps_s, flags_s) returns (same support, coefficients up to FP32
+ * rounding order).
+ *
+ * sc_scene: one scene.  dict: handle with K <= 512 on the current device;
+ * X: device N x d float32; k: 1 <= k <= min(K, d, 16); eps >= 0 finite;
+ * flags: SC_EPS_RELATIVE, SC_NO_FP64_REFIT; outputs as sc_omp_encode (resid
+ * may be NULL; with N = 0 the pointers may be NULL).  Caller-owned.
+ */
+#define SC_MAX_SCENES 32
+typedef struct {
+    sc_dict dict;
+    const float *X;
+    int64_t N;
+    int k;
+    float eps;
+    int flags;
+    int32_t *idx;
+    float *coef;
+    int32_t *count;
+    float *resid;
+} sc_scene;
+
+/*
+ * sc_batch_tuning: launch shape of the batched encoder (results do not
+ * depend on it beyond FP32 rounding order).
+ *   tile       signals per workgroup tile: 16 or 32 (0 = 16)
+ *   row_cache  Gram rows kept in registers: 0 or 4
+ *   wg_per_cu  persistent workgroups per compute unit, 0 = as many as fit
+ *   order      SC_ORDER_COST: scenes taken most expensive tile first;
+ *              SC_ORDER_GIVEN: in the order of the array
+ *   corr       correlation stage of every scene: SC_CORR_VALU or SC_CORR_MFMA
+ */
+#define SC_ORDER_COST 0
+#define SC_ORDER_GIVEN 1
+typedef struct {
+    int tile;
+    int row_cache;
+    int wg_per_cu;
+    int order;
+    int corr;
+} sc_batch_tuning;
+
+/* Device workspace bytes the batched encoder needs (a work counter). */
+size_t sc_omp_encode_batched_workspace(void);
+
+/*
+ * sc_omp_encode_batched -- encode n_scenes (1..SC_MAX_SCENES) scenes in one
+ * stream-ordered launch (plus an FP64-refit scan when a scene allows it).
+ *   tuning     NULL: tile 16, row_cache 0, all workgroups that fit, cost
+ *              order, VALU correlations
+ *   workspace  device, >= sc_omp_encode_batched_workspace() bytes; calls
+ *              sharing a workspace must not overlap in time
+ * No allocation.  Errors: SC_EINVAL (a scene or the tuning out of range, or
+ * dictionaries on different devices), SC_ENOMEM (workspace too small),
+ * SC_EDEVICE.
+ */
+int sc_omp_encode_batched(const sc_scene *scenes, int n_scenes, const sc_batch_tuning *tuning, void *workspace,
+                          size_t ws_bytes, void *stream);
+
+/*
+ * sc_batch_autotune -- the project's autotuner for sc_omp_encode_batched:
+ * runs the batched encoder on the first min(N_s, sample) signals of every
+ * scene (writing those outputs) and times each launch shape with HIP events
+ * on `stream`: every combination of corr x tile x row_cache x wg_per_cu
+ * (0, 1, 2) x order.  Writes the fastest shape to *best and its time (ms,
+ * best of 2 after a warm-up launch) to *best_ms.  Synchronises the stream.
+ * Errors: as sc_omp_encode_batched; sample must be >= 1.
+ */
+int sc_batch_autotune(const sc_scene *scenes, int n_scenes, int64_t sample, void *workspace, size_t ws_bytes,
+                      sc_batch_tuning *best, float *best_ms, void *stream);
 
 #ifdef __cplusplus
 }

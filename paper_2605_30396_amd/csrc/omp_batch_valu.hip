@@ -1,0 +1,11 @@
+// Batch-OMP kernels with the A0_VALU correlation stage.
+#include "omp_batch_impl.h"
+
+namespace sc {
+
+hipError_t launch_omp_batch_valu(const DictDev &dict, const OmpParams &p, int kmax, int row_cache,
+                                 hipStream_t st) {
+    return launch_batch_mode<A0_VALU>(dict, p, kmax, row_cache, st);
+}
+
+}  // namespace sc

@@ -1,0 +1,559 @@
+// Batch-OMP tile encoder on gfx950, shared by the single-dictionary kernel
+// and the multi-scene persistent kernel.
+//
+// OMP (Sec. 2.1, Eq. (1)) picks, step by step, the atom most correlated with
+// the residual and refits x on the picked atoms by least squares.  Batch-OMP
+// reaches the same codes from alpha0 = D^T x and the Gram matrix G = D^T D
+// without forming the residual:
+//
+//   alpha = alpha0 - G_I gamma                 (correlations of the residual)
+//   j     = argmax_{j not in I} |alpha_j|
+//   w     = L^-1 G[I, j],  l = sqrt(G_jj - |w|^2)      (new row of chol(G_II))
+//   c_n   = (alpha0_j - w . c) / l                     (c = L^-1 alpha0_I)
+//   ||r||^2 -= c_n^2
+//   gamma = L^-T c                                     (back substitution)
+//
+// One 64-lane wave encodes one signal.  Lane l owns atoms l*E .. l*E+E-1
+// (Kp = 64 E) of alpha0; the Gram rows of the selected atoms are re-read
+// (from L2) whenever alpha is formed, so the per-wave register state is
+// O(E + k) and many waves fit on a SIMD.  Lane t keeps step t's scalars
+// (atom, c_t, 1/L_tt, gamma_t), row t of L and column t of L, so both
+// triangular solves run lane-parallel with one v_readlane per step.
+//
+// Selection key: the bits of |alpha_j| with the low 10 mantissa bits replaced
+// by (1023 - j), so one unsigned wave maximum gives the atom, and entries
+// whose magnitudes agree to 2^-13 relative resolve to the lowest index.
+// Selected and padding atoms have their magnitude bits masked off.
+//
+// A support whose Cholesky condition estimate (max L_ii / min L_ii)^2 exceeds
+// kappa_max leaves count = -(2 + n) and the FP32 coefficients; a separate
+// pass (refit_scan) solves it again in FP64 and writes the final count.
+#pragma once
+#include "mfma.h"
+#include "sc_internal.h"
+#include "wave.h"
+
+namespace sc {
+
+constexpr int kOmpWaves = 4;
+constexpr int kOmpThreads = 64 * kOmpWaves;
+constexpr int kXhs = 72;                              // LDS row stride (BF16) of the split signal tile
+constexpr uint32_t kKeyIdx = 1023u;                   // atom index bits of a selection key
+constexpr uint32_t kKeyMag = 0x7FFFFFFFu & ~kKeyIdx;  // magnitude bits of a selection key
+
+// LDS bytes of one workgroup: alpha0 tile [T][Kp], signal tile [64][T], and
+// for the split-BF16 correlations the two BF16 signal parts [T][kXhs].
+__host__ __device__ constexpr size_t omp_tile_lds(int T, int Kp, bool split) {
+    return sizeof(float) * ((size_t)T * Kp + 64 * (size_t)T) + (split ? sizeof(uint16_t) * 2 * T * kXhs : 0);
+}
+
+struct OmpTally {
+    unsigned long long sig = 0, atoms = 0;
+};
+
+// Signals s0 .. s0+nt-1 of the call (through `rows` when given), stored
+// feature-major Xt[i][s]; features >= d and columns >= nt are zero.
+template <int T>
+__device__ __forceinline__ void load_tile(const OmpParams &p, int d, int64_t s0, int nt, float *Xt, int tid) {
+    if (p.rows) {
+        for (int f = tid; f < nt * d; f += kOmpThreads) {
+            const int s = f / d, i = f - s * d;
+            Xt[i * T + s] = p.X[(int64_t)p.rows[s0 + s] * d + i];
+        }
+    } else {
+        const float *__restrict__ Xtile = p.X + s0 * d;
+        for (int f = tid; f < nt * d; f += kOmpThreads) {
+            const int s = f / d, i = f - s * d;
+            Xt[i * T + s] = Xtile[f];
+        }
+    }
+    for (int q = tid; q < 64 * T; q += kOmpThreads) {
+        const int i = q / T, s = q - i * T;
+        if (i >= d || s >= nt) Xt[q] = 0.f;
+    }
+}
+
+// alpha0 tile on VALU: A0[s][j] = sum_i DT[i][j] Xt[i][s].
+template <int E, int T>
+__device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d, const float *__restrict__ Xt,
+                                            float *__restrict__ A0, int tid) {
+    constexpr int Kp = 64 * E;
+    constexpr int KpP = Kp < kOmpThreads ? Kp : kOmpThreads;   // atoms covered by one pass of the workgroup
+    constexpr int SG = kOmpThreads / KpP;                      // signal groups
+    constexpr int JS = Kp / KpP;                               // atom slots per thread
+    constexpr int SQ = T / SG;                                 // signals per thread
+    static_assert(Kp % KpP == 0 && T % SG == 0, "tile shape");
+    const int j0 = tid % KpP, sg = tid / KpP;
+    float acc[JS][SQ];
+#pragma unroll
+    for (int r = 0; r < JS; ++r)
+#pragma unroll
+        for (int q = 0; q < SQ; ++q) acc[r][q] = 0.f;
+    for (int i = 0; i < d; ++i) {
+        float dv[JS];
+#pragma unroll
+        for (int r = 0; r < JS; ++r) dv[r] = DT[(size_t)i * Kp + j0 + r * KpP];
+#pragma unroll
+        for (int q = 0; q < SQ; ++q) {
+            const float xv = Xt[i * T + sg + q * SG];
+#pragma unroll
+            for (int r = 0; r < JS; ++r) acc[r][q] = fmaf(dv[r], xv, acc[r][q]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < JS; ++r)
+#pragma unroll
+        for (int q = 0; q < SQ; ++q) A0[(sg + q * SG) * Kp + j0 + r * KpP] = acc[r][q];
+}
+
+// alpha0 tile on FP32 MFMA (v_mfma_f32_16x16x4_f32): wave w computes the
+// 16-atom blocks w, w+4, ... for every 16-signal column block.  A operand:
+// 16 atoms x 4 features read from the feature-major dictionary; B operand:
+// 4 features x 16 signals from the LDS signal tile.
+template <int E, int T>
+__device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ DT, int d, const float *__restrict__ Xt,
+                                                float *__restrict__ A0, int wave, int lane) {
+    constexpr int Kp = 64 * E, MT = Kp / 16, NB = MT / kOmpWaves, CB = T / 16;
+    static_assert(T % 16 == 0, "MFMA tile needs 16-signal column blocks");
+    const int lr = lane & 15, kq = lane >> 4;
+    floatx4 acc[NB][CB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int dk = (d + 3) & ~3;
+#pragma unroll 2
+    for (int k0 = 0; k0 < dk; k0 += 4) {
+        const int f = k0 + kq;
+        float bx[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) bx[c] = Xt[f * T + c * 16 + lr];
+        const float *row = DT + (size_t)(f < d ? f : 0) * Kp + lr;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float a = f < d ? row[(wave + kOmpWaves * b) * 16] : 0.f;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bx[c], acc[b][c], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            *reinterpret_cast<floatx4 *>(A0 + (c * 16 + lr) * Kp + (wave + kOmpWaves * b) * 16 + 4 * kq) = acc[b][c];
+}
+
+// alpha0 tile (16 signals) as the split BF16 product Dh xh + Dl xh + Dh xl,
+// features padded to 64 (v_mfma_f32_16x16x32_bf16); relative error ~2^-16.
+template <int E>
+__device__ __forceinline__ void alpha0_mfma_bf16x3(const uint16_t *__restrict__ Dh, const uint16_t *__restrict__ Dl,
+                                                   const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xl,
+                                                   float *__restrict__ A0, int wave, int lane) {
+    constexpr int Kp = 64 * E, MT = Kp / 16, NB = MT / kOmpWaves;
+    const int lr = lane & 15, kq = lane >> 4;
+    floatx4 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < 64; k0 += 32) {
+        const bf16x8 bh = ld_bf16x8(Xh + lr * kXhs + k0 + 8 * kq);
+        const bf16x8 bl = ld_bf16x8(Xl + lr * kXhs + k0 + 8 * kq);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int atom = (wave + kOmpWaves * b) * 16 + lr;
+            const bf16x8 ah = ld_bf16x8(Dh + (size_t)atom * 64 + k0 + 8 * kq);
+            const bf16x8 al = ld_bf16x8(Dl + (size_t)atom * 64 + k0 + 8 * kq);
+            acc[b] = mfma16(al, bh, acc[b]);
+            acc[b] = mfma16(ah, bl, acc[b]);
+            acc[b] = mfma16(ah, bh, acc[b]);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        *reinterpret_cast<floatx4 *>(A0 + lr * Kp + (wave + kOmpWaves * b) * 16 + 4 * kq) = acc[b];
+}
+
+// The E Gram-row entries of this lane (16-byte aligned for E % 4 == 0).
+template <int E>
+__device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)[E]) {
+    if constexpr (E % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) {
+            const float4 f = reinterpret_cast<const float4 *>(p)[q];
+            v[4 * q] = f.x;
+            v[4 * q + 1] = f.y;
+            v[4 * q + 2] = f.z;
+            v[4 * q + 3] = f.w;
+        }
+    } else if constexpr (E == 2) {
+        const float2 f = *reinterpret_cast<const float2 *>(p);
+        v[0] = f.x;
+        v[1] = f.y;
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = p[e];
+    }
+}
+
+// Encodes signal `sig` (column s of the tile) with one wave.  kSplit: alpha0
+// holds the split-BF16 correlations, and alpha0_j of a selected atom is
+// recomputed in FP32 from the signal, so the coefficients, the tracked
+// residual and the stop test carry no BF16 error.
+// RCQ: the Gram rows of the atoms of the first RCQ steps are kept in
+// registers (RCQ * E VGPRs); later rows are re-read whenever alpha is formed.
+template <int E, int KMAX, bool kSplit, int T, int RCQ>
+__device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams &p, int64_t sig, int s,
+                                            const float *__restrict__ Xt, const float *__restrict__ A0, int lane,
+                                            OmpTally &tally) {
+    constexpr int Kp = 64 * E;
+    constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
+    const int d = dict.d, K = dict.K, k = p.k;
+    const float *__restrict__ G = dict.G;
+    const float *__restrict__ Dg = dict.D;
+    const float xv = lane < d ? Xt[lane * T + s] : 0.f;
+    int32_t *oidx = p.idx + sig * k;
+    float *ocoef = p.coef + sig * k;
+    if (ballot(lane < d && !isfinite(xv)) != 0) {   // status -1, padded slots
+        if (lane < k) {
+            oidx[lane] = -1;
+            ocoef[lane] = 0.f;
+        }
+        if (lane == 0) {
+            p.count[sig] = -1;
+            if (p.resid) p.resid[sig] = __builtin_nanf("");
+        }
+        return;
+    }
+    const float xx = wave_sum(xv * xv);
+    const float xnorm = sqrtf(xx);
+    const float eps_abs = p.relative ? p.eps * xnorm : p.eps;
+    const float eps2 = eps_abs * eps_abs;
+    const float band = 1e-5f * xx;     // FP32 uncertainty of the tracked ||r||^2
+    const float brk = 1e-6f * xnorm;   // residual orthogonal to every atom
+
+    float a0[E];
+    uint32_t msk[E], kid[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = lane * E + e;
+        const bool real = j < K;
+        a0[e] = real ? A0[s * Kp + j] : 0.f;
+        msk[e] = real ? kKeyMag : 0u;
+        kid[e] = kKeyIdx - (uint32_t)j;
+    }
+    float Lrow[KMAX], Lcol[KMAX];   // lane t: L[t][u] (u < t) and L[u][t] (u > t)
+#pragma unroll
+    for (int u = 0; u < KMAX; ++u) {
+        Lrow[u] = 0.f;
+        Lcol[u] = 0.f;
+    }
+    float cval = 0.f, linv = 1.f, gam = 0.f;   // lane t: c_t, 1 / L_tt, gamma_t
+    int selv = 0;                               // lane t: atom of step t
+    float rc[RC > 0 ? RC : 1][E];   // G rows of the atoms of steps t < RC
+    float rr = xx, lmax = 0.f, lmin = 3.4e38f, rr_expl = 0.f;
+    int n = 0, n_gam = -1;   // gamma is current for n_gam atoms
+    bool active = xx > 0.f, expl_done = false;
+
+    // gamma = L^-T c for the first nn atoms
+    auto back_sub = [&](int nn) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = KMAX - 1; t >= 0; --t) {
+            if (t < nn) {
+                const float gt = readlane_f((cval - acc) * linv, t);
+                gam = lane == t ? gt : gam;
+                acc = fmaf(Lcol[t], gt, acc);
+            }
+        }
+        n_gam = nn;
+    };
+    // ||x - D_I gamma||^2 with the current gamma (lane i < d holds x_i)
+    auto resid2 = [&](int nn) {
+        float r = xv;
+        nn = __builtin_amdgcn_readfirstlane(nn);
+        asm volatile("" : "+s"(nn));
+#pragma unroll 2
+        for (int t = 0; t < nn; ++t) {
+            const int jt = readlane_i(selv, t);
+            const float gt = readlane_f(gam, t);
+            if (lane < d) r = fmaf(-Dg[(size_t)jt * d + lane], gt, r);
+        }
+        return wave_sum(lane < d ? r * r : 0.f);
+    };
+
+    // Unrolled over the sparsity cap so the per-step arrays stay in
+    // registers; `active` skips the remaining steps uniformly.
+#pragma unroll
+    for (int it = 0; it < KMAX; ++it) {
+        if (!active) continue;
+        if (it >= k) {
+            active = false;
+            continue;
+        }
+        // ---- stop test before the selection ----
+        if (eps2 > 0.f) {
+            if (rr <= eps2 - band) {
+                active = false;
+                continue;
+            }
+            if (rr <= eps2 + band) {   // too close to call on the tracked value
+                back_sub(it);
+                const float re = resid2(it);
+                if (re <= eps2) {
+                    expl_done = true;
+                    rr_expl = re;
+                    active = false;
+                    continue;
+                }
+            }
+        }
+        // ---- correlations of the residual and the selection ----
+        if (n_gam != it) back_sub(it);
+        float al[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) al[e] = a0[e];
+#pragma unroll
+        for (int t = 0; t < (it < RC ? it : RC); ++t) {
+            const float gt = readlane_f(gam, t);
+#pragma unroll
+            for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, rc[t][e], al[e]);
+        }
+        // rows past the cache: a real loop keeps at most two in flight (the
+        // trip count is hidden from the optimiser, which would otherwise
+        // unroll it fully and issue every row load at once)
+        int nrow = it;
+        asm volatile("" : "+s"(nrow));
+#pragma unroll 2
+        for (int t = RC; t < nrow; ++t) {
+            const int jt = readlane_i(selv, t);
+            const float gt = readlane_f(gam, t);
+            float gr[E];
+            load_row<E>(G + (size_t)jt * Kp + lane * E, gr);
+#pragma unroll
+            for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[e], al[e]);
+        }
+        uint32_t best = 0u;
+#pragma unroll
+        for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & msk[e]) | kid[e]);
+        const uint32_t kb = wave_max_u32(best);
+        if (!(__uint_as_float(kb & kKeyMag) > brk)) {
+            active = false;
+            continue;
+        }
+        const int j = (int)(kKeyIdx - (kb & kKeyIdx));
+        if (it < RC) load_row<E>(G + (size_t)j * Kp + lane * E, rc[it < RC ? it : 0]);
+        // ---- new row of the Cholesky factor: L w = G[I, j] ----
+        float g = 0.f;
+        if (lane < it) g = G[(size_t)selv * Kp + j];
+        const float gjj = G[(size_t)j * Kp + j];
+        float acc = 0.f, wsq = 0.f, wc = 0.f, wv = 0.f;
+#pragma unroll
+        for (int t = 0; t < it; ++t) {
+            const float wt = readlane_f((g - acc) * linv, t);
+            acc = fmaf(Lrow[t], wt, acc);
+            wsq = fmaf(wt, wt, wsq);
+            wc = fmaf(wt, readlane_f(cval, t), wc);
+            wv = lane == t ? wt : wv;
+            Lrow[t] = lane == it ? wt : Lrow[t];
+        }
+        const float l2 = gjj - wsq;
+        if (!(l2 > 1e-9f * gjj)) {   // numerically dependent on the selected atoms
+            active = false;
+            continue;
+        }
+        const float ell = sqrtf(l2);
+        const float inv = __builtin_amdgcn_rcpf(ell);
+        float zj;
+        if constexpr (kSplit)
+            zj = wave_sum(lane < d ? Dg[(size_t)j * d + lane] * xv : 0.f);
+        else
+            zj = A0[s * Kp + j];
+        const float cn = (zj - wc) * inv;
+        rr = fmaf(-cn, cn, rr);
+        lmax = fmaxf(lmax, ell);
+        lmin = fminf(lmin, ell);
+        Lcol[it] = wv;
+        if (lane == it) {
+            cval = cn;
+            linv = inv;
+            selv = j;
+        }
+        // retire atom j from the selection
+        const int jl = j / E, je = j - jl * E;
+#pragma unroll
+        for (int e = 0; e < E; ++e) msk[e] = (lane == jl && e == je) ? 0u : msk[e];
+        n = it + 1;
+    }
+
+    // ---- coefficients, residual, outputs ----
+    if (n_gam != n) back_sub(n);
+    bool refit = false;
+    if (n > 0 && p.fp64_refit) {
+        const float q = lmax / lmin;
+        refit = q * q > p.kappa_max;
+    }
+    float re = 0.f;
+    if (!refit) re = expl_done ? rr_expl : resid2(n);
+    if (lane < k) {
+        oidx[lane] = lane < n ? selv : -1;
+        ocoef[lane] = lane < n ? gam : 0.f;
+    }
+    if (lane == 0) {
+        p.count[sig] = refit ? -(2 + n) : n;
+        if (p.resid) p.resid[sig] = refit ? 0.f : sqrtf(re);
+    }
+    tally.sig += 1;
+    tally.atoms += n;
+}
+
+// One tile of T signals: load, alpha0 by `mode` (A0_VALU or A0_MFMA_F32; or
+// A0_MFMA_BF16X3 when kSplitOK, T == 16 and the LDS holds the split parts),
+// then each wave encodes its signals.
+template <int E, int KMAX, int T, bool kSplitOK, int RCQ>
+__device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p, int mode, int64_t s0, int nt,
+                                         unsigned char *smem, int tid, OmpTally &tally) {
+    constexpr int Kp = 64 * E;
+    float *A0 = reinterpret_cast<float *>(smem);
+    float *Xt = A0 + T * Kp;
+    const int lane = tid & 63, wave = tid >> 6;
+    __syncthreads();   // the previous tile is done with Xt and A0
+    load_tile<T>(p, dict.d, s0, nt, Xt, tid);
+    __syncthreads();
+    bool split = false;
+    if (mode == A0_MFMA_F32) {
+        alpha0_mfma_f32<E, T>(dict.DT, dict.d, Xt, A0, wave, lane);
+    } else if (kSplitOK && T == 16 && mode == A0_MFMA_BF16X3) {
+        uint16_t *Xh = reinterpret_cast<uint16_t *>(Xt + 64 * T);
+        uint16_t *Xl = Xh + T * kXhs;
+        for (int q = tid; q < T * 64; q += kOmpThreads) {
+            const int s = q >> 6, f = q & 63;
+            const float v = Xt[f * T + s];
+            const uint16_t hi = bf16_bits(v);
+            Xh[s * kXhs + f] = hi;
+            Xl[s * kXhs + f] = bf16_bits(v - bf16_to_f32(hi));
+        }
+        __syncthreads();
+        alpha0_mfma_bf16x3<E>(dict.Dbf, dict.Dlo, Xh, Xl, A0, wave, lane);
+        split = true;
+    } else {
+        alpha0_valu<E, T>(dict.DT, dict.d, Xt, A0, tid);
+    }
+    __syncthreads();
+    for (int s = wave; s < nt; s += kOmpWaves) {
+        const int64_t sig = p.rows ? (int64_t)p.rows[s0 + s] : s0 + s;
+        if (kSplitOK && split)
+            omp_pursuit<E, KMAX, kSplitOK, T, RCQ>(dict, p, sig, s, Xt, A0, lane, tally);
+        else
+            omp_pursuit<E, KMAX, false, T, RCQ>(dict, p, sig, s, Xt, A0, lane, tally);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 refit of flagged supports
+// ---------------------------------------------------------------------------
+
+constexpr int kRefitMax = 32;
+
+struct RefitScratch {
+    int sel[kRefitMax];
+    double z[kRefitMax];
+    double Gd[kRefitMax * kRefitMax];
+};
+
+// G_II gamma = D_I^T x with G_II and D_I^T x summed in FP64, solved by
+// Cholesky (lane 0); writes gamma, the explicit residual and count = n.
+__device__ __forceinline__ void refit_one(const DictDev &dict, const OmpParams &p, int64_t sig, int n,
+                                          RefitScratch &ws, int lane) {
+    const int d = dict.d, k = p.k;
+    const float *__restrict__ D = dict.D;
+    const float *__restrict__ x = p.X + sig * d;
+    if (lane < n) ws.sel[lane] = p.idx[sig * k + lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = lane; q < n * n; q += 64) {
+        const int t = q / n, u = q - t * n;
+        const float *a = D + (size_t)ws.sel[t] * d;
+        const float *b = D + (size_t)ws.sel[u] * d;
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) s += (double)a[i] * (double)b[i];
+        ws.Gd[t * kRefitMax + u] = s;
+    }
+    if (lane < n) {
+        const float *a = D + (size_t)ws.sel[lane] * d;
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) s += (double)a[i] * (double)x[i];
+        ws.z[lane] = s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {
+        double *Gd = ws.Gd, *z = ws.z;
+        for (int t = 0; t < n; ++t) {   // G = R R^T, R lower, in place
+            for (int u = 0; u <= t; ++u) {
+                double s = Gd[t * kRefitMax + u];
+                for (int v = 0; v < u; ++v) s -= Gd[t * kRefitMax + v] * Gd[u * kRefitMax + v];
+                Gd[t * kRefitMax + u] = (u == t) ? sqrt(fmax(s, 1e-300)) : s / Gd[u * kRefitMax + u];
+            }
+        }
+        for (int t = 0; t < n; ++t) {   // R y = z
+            double s = z[t];
+            for (int u = 0; u < t; ++u) s -= Gd[t * kRefitMax + u] * z[u];
+            z[t] = s / Gd[t * kRefitMax + t];
+        }
+        for (int t = n - 1; t >= 0; --t) {   // R^T gamma = y
+            double s = z[t];
+            for (int u = t + 1; u < n; ++u) s -= Gd[u * kRefitMax + t] * z[u];
+            z[t] = s / Gd[t * kRefitMax + t];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double r = 0.0;
+    if (lane < d) {
+        r = (double)x[lane];
+        for (int t = 0; t < n; ++t) r -= ws.z[t] * (double)D[(size_t)ws.sel[t] * d + lane];
+    }
+    const double r2 = wave_sum_d(lane < d ? r * r : 0.0);
+    if (lane < n) p.coef[sig * k + lane] = (float)ws.z[lane];
+    if (lane == 0) {
+        p.count[sig] = n;
+        if (p.resid) p.resid[sig] = (float)sqrt(r2);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Scans the call's signals in chunks of 64 (wave `gw` of `nw` waves) and
+// refits those flagged with count = -(2 + n).  Returns the number refit.
+__device__ __forceinline__ unsigned long long refit_scan(const DictDev &dict, const OmpParams &p, int64_t gw,
+                                                         int64_t nw, RefitScratch &ws, int lane) {
+    int64_t Nsig = p.N;
+    if (p.rows) Nsig = min<int64_t>(Nsig, (int64_t)*p.nrows);
+    const int64_t nchunks = (Nsig + 63) / 64;
+    unsigned long long nref = 0;
+    for (int64_t c = gw; c < nchunks; c += nw) {
+        const int64_t i = c * 64 + lane;
+        int64_t sig = 0;
+        int cnt = 0;
+        if (i < Nsig) {
+            sig = p.rows ? (int64_t)p.rows[i] : i;
+            cnt = p.count[sig];
+        }
+        uint64_t flagged = ballot(cnt < -1);
+        while (flagged) {
+            const int l = __ffsll((unsigned long long)flagged) - 1;
+            flagged &= flagged - 1;
+            const int lo = __builtin_amdgcn_readlane((int)(sig & 0xFFFFFFFF), l);
+            const int hi = __builtin_amdgcn_readlane((int)(sig >> 32), l);
+            const int64_t sg = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+            const int nn = -__builtin_amdgcn_readlane(cnt, l) - 2;
+            refit_one(dict, p, sg, nn, ws, lane);
+            nref += 1;
+        }
+    }
+    return nref;
+}
+
+}  // namespace sc

@@ -53,6 +53,7 @@ void free_dict(sc_dict h) {
     hipFree(h->D48);
     hipFree(h->status);
     hipFree(h->stats);
+    hipFree(h->ddev);
     delete h;
 }
 
@@ -125,6 +126,13 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
         return set_dev_error("sc_gram_precompute", e);
     }
     h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->D48};
+    h->row_cache = E <= 4 ? 4 : 0;
+    // device copy of the layout descriptor, read by the multi-scene encoder
+    if ((e = hipMalloc(&h->ddev, sizeof(sc::DictDev))) != hipSuccess ||
+        (e = hipMemcpy(h->ddev, &h->dev, sizeof(sc::DictDev), hipMemcpyHostToDevice)) != hipSuccess) {
+        free_dict(h);
+        return set_dev_error("sc_gram_precompute", e);
+    }
     *out = h;
     return SC_OK;
 }
@@ -166,7 +174,7 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
                     (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, idx, coef, count, resid, h->stats};
     hipStream_t st = (hipStream_t)stream;
     const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
-    hipError_t e = sc::launch_omp_batch(h->dev, p, kmax, a0, st);
+    hipError_t e = sc::launch_omp_batch(h->dev, p, kmax, a0, h->row_cache, st);
     if (e == hipErrorInvalidValue) {
         snprintf(g_last_error, sizeof(g_last_error), "no compiled encoder for K=%d (Kp=%d) with k=%d", K,
                  h->dev.Kp, k);
@@ -183,6 +191,11 @@ int sc_dict_set_tuning(sc_dict h, int key, int value) {
         h->a0_fp32 = value == SC_CORR_VALU ? sc::A0_VALU : sc::A0_MFMA_F32;
         return SC_OK;
     }
+    if (key == SC_TUNE_ROW_CACHE) {
+        if (value != 0 && value != 4) return SC_EINVAL;
+        h->row_cache = value;
+        return SC_OK;
+    }
     return SC_EINVAL;
 }
 
@@ -190,6 +203,10 @@ int sc_dict_get_tuning(sc_dict h, int key, int *value) {
     if (!h || !value) return SC_EINVAL;
     if (key == SC_TUNE_FP32_CORRELATION) {
         *value = h->a0_fp32 == sc::A0_VALU ? SC_CORR_VALU : SC_CORR_MFMA;
+        return SC_OK;
+    }
+    if (key == SC_TUNE_ROW_CACHE) {
+        *value = h->row_cache;
         return SC_OK;
     }
     return SC_EINVAL;
@@ -354,7 +371,7 @@ int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, i
     SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, kmax, st), "sc_omp_encode_learned (restricted)");
     sc::OmpParams fp{X, N, miss_rows, miss_count, k, eps, rel, refit, kKappaMax, idx, coef, count, resid, h->stats};
     const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
-    SC_HIP(sc::launch_omp_batch(h->dev, fp, kmax, a0, st), "sc_omp_encode_learned (fallback)");
+    SC_HIP(sc::launch_omp_batch(h->dev, fp, kmax, a0, h->row_cache, st), "sc_omp_encode_learned (fallback)");
     return SC_OK;
 }
 
@@ -390,9 +407,156 @@ int sc_omp_encode_rows(sc_dict h, const float *X, const int32_t *rows, const int
     sc::OmpParams p{X, max_rows, rows, nrows, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0,
                     (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, idx, coef, count, resid, h->stats};
     const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
-    hipError_t e = sc::launch_omp_batch(h->dev, p, sc::pick_kmax(k), a0, (hipStream_t)stream);
+    hipError_t e = sc::launch_omp_batch(h->dev, p, sc::pick_kmax(k), a0, h->row_cache, (hipStream_t)stream);
     if (e == hipErrorInvalidValue) return SC_EINVAL;
     if (e != hipSuccess) return set_dev_error("sc_omp_encode_rows", e);
+    return SC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* many scenes in one launch                                            */
+/* ------------------------------------------------------------------ */
+
+namespace {
+
+constexpr size_t kBatchWorkspace = 256;
+
+int validate_scenes(const sc_scene *scenes, int n) {
+    if (!scenes || n < 1 || n > SC_MAX_SCENES) return SC_EINVAL;
+    int dev = -1;
+    for (int q = 0; q < n; ++q) {
+        const sc_scene &s = scenes[q];
+        const sc_dict h = s.dict;
+        if (!h || s.N < 0) return SC_EINVAL;
+        if (dev < 0) dev = h->device;
+        if (h->device != dev) return SC_EINVAL;
+        const int d = h->dev.d, K = h->dev.K;
+        if (h->dev.E > 8 || s.k < 1 || s.k > std::min(std::min(K, d), 16)) return SC_EINVAL;
+        if (!(s.eps >= 0.f) || !isfinite(s.eps)) return SC_EINVAL;
+        if (s.flags & ~(SC_EPS_RELATIVE | SC_NO_FP64_REFIT)) return SC_EINVAL;
+        if (s.N > 0 && (!s.X || !s.idx || !s.coef || !s.count)) return SC_EINVAL;
+    }
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != dev) return SC_EINVAL;
+    return SC_OK;
+}
+
+int validate_tuning(const sc_batch_tuning *t, int n) {
+    if (!t) return SC_OK;
+    if (t->tile != 0 && t->tile != 16 && t->tile != 32) return SC_EINVAL;
+    if (t->row_cache != 0 && t->row_cache != 4) return SC_EINVAL;
+    if (t->wg_per_cu < 0 || t->wg_per_cu > 64) return SC_EINVAL;
+    if (t->order != SC_ORDER_COST && t->order != SC_ORDER_GIVEN) return SC_EINVAL;
+    if (t->corr != SC_CORR_VALU && t->corr != SC_CORR_MFMA) return SC_EINVAL;
+    (void)n;
+    return SC_OK;
+}
+
+sc_batch_tuning default_tuning() {
+    sc_batch_tuning t;
+    t.tile = 16;
+    t.row_cache = 0;
+    t.wg_per_cu = 0;
+    t.order = SC_ORDER_COST;
+    t.corr = SC_CORR_VALU;
+    return t;
+}
+
+// Launch on validated arguments.
+int encode_batched(const sc_scene *scenes, int n, const sc_batch_tuning &t, int *counter, hipStream_t st) {
+    int order[SC_MAX_SCENES];
+    double cost[SC_MAX_SCENES];
+    int m = 0;
+    for (int q = 0; q < n; ++q) {
+        const sc_dict h = scenes[q].dict;
+        // work of a tile: the correlations (Kp d) and the pursuit (~Kp per step)
+        cost[q] = (double)h->dev.Kp * (h->dev.d + 4.0 * std::min(scenes[q].k, 8));
+        if (scenes[q].N > 0) order[m++] = q;
+    }
+    if (m == 0) return SC_OK;
+    if (t.order == SC_ORDER_COST)
+        std::stable_sort(order, order + m, [&](int a, int b) { return cost[a] > cost[b]; });
+    hipError_t e = sc::launch_omp_multi(scenes, order, m, t.corr == SC_CORR_MFMA ? sc::A0_MFMA_F32 : sc::A0_VALU,
+                                        t.tile == 32 ? 32 : 16, t.row_cache, t.wg_per_cu, counter, st);
+    if (e != hipSuccess) return set_dev_error("sc_omp_encode_batched", e);
+    return SC_OK;
+}
+
+}  // namespace
+
+size_t sc_omp_encode_batched_workspace(void) { return kBatchWorkspace; }
+
+int sc_omp_encode_batched(const sc_scene *scenes, int n_scenes, const sc_batch_tuning *tuning, void *workspace,
+                          size_t ws_bytes, void *stream) {
+    int rc = validate_scenes(scenes, n_scenes);
+    if (rc != SC_OK) return rc;
+    if ((rc = validate_tuning(tuning, n_scenes)) != SC_OK) return rc;
+    if (!workspace) return SC_EINVAL;
+    if (ws_bytes < kBatchWorkspace) return SC_ENOMEM;
+    return encode_batched(scenes, n_scenes, tuning ? *tuning : default_tuning(), (int *)workspace,
+                          (hipStream_t)stream);
+}
+
+int sc_batch_autotune(const sc_scene *scenes, int n_scenes, int64_t sample, void *workspace, size_t ws_bytes,
+                      sc_batch_tuning *best, float *best_ms, void *stream) {
+    int rc = validate_scenes(scenes, n_scenes);
+    if (rc != SC_OK) return rc;
+    if (!workspace || !best || sample < 1) return SC_EINVAL;
+    if (ws_bytes < kBatchWorkspace) return SC_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    int *counter = (int *)workspace;
+    sc_scene tr[SC_MAX_SCENES];
+    for (int q = 0; q < n_scenes; ++q) {
+        tr[q] = scenes[q];
+        tr[q].N = std::min<int64_t>(scenes[q].N, sample);
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return set_dev_error("sc_batch_autotune", hipErrorUnknown);
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return set_dev_error("sc_batch_autotune", hipErrorUnknown);
+    }
+    int err = SC_OK;
+    // best of 2 timed launches after a warm-up; +inf on failure
+    auto timeit = [&](const sc_scene *sc_, int n, const sc_batch_tuning &t) -> float {
+        float bestt = 3.4e38f;
+        for (int r = 0; r < 3 && err == SC_OK; ++r) {
+            if (hipEventRecord(e0, st) != hipSuccess) err = SC_EDEVICE;
+            if (err == SC_OK) err = encode_batched(sc_, n, t, counter, st);
+            if (err == SC_OK && hipEventRecord(e1, st) != hipSuccess) err = SC_EDEVICE;
+            if (err == SC_OK && hipEventSynchronize(e1) != hipSuccess) err = SC_EDEVICE;
+            float ms = 0.f;
+            if (err == SC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) err = SC_EDEVICE;
+            if (err == SC_OK && r > 0) bestt = std::min(bestt, ms);
+        }
+        return bestt;
+    };
+    sc_batch_tuning bt = default_tuning();
+    float bms = 3.4e38f;
+    const int corrs[2] = {SC_CORR_VALU, SC_CORR_MFMA}, tiles[2] = {16, 32}, rcs[2] = {0, 4}, wgs[3] = {0, 1, 2},
+              orders[2] = {SC_ORDER_COST, SC_ORDER_GIVEN};
+    for (int m = 0; m < 2; ++m)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 3; ++c)
+                    for (int o = 0; o < 2 && err == SC_OK; ++o) {
+                        sc_batch_tuning t = default_tuning();
+                        t.corr = corrs[m];
+                        t.tile = tiles[a];
+                        t.row_cache = rcs[b];
+                        t.wg_per_cu = wgs[c];
+                        t.order = orders[o];
+                        const float ms = timeit(tr, n_scenes, t);
+                        if (ms < bms) {
+                            bms = ms;
+                            bt = t;
+                        }
+                    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (err != SC_OK) return err;
+    *best = bt;
+    if (best_ms) *best_ms = bms;
     return SC_OK;
 }
 

@@ -91,7 +91,14 @@ hipError_t launch_dict_check(const float *D, int d, int K, int normalize, float 
 hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *DT, uint16_t *Dbf, uint16_t *Dlo,
                                float *D48, hipStream_t st);
 hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, hipStream_t st);
-hipError_t launch_omp_batch(const DictDev &dict, const OmpParams &p, int kmax, int a0mode, hipStream_t st);
+hipError_t launch_omp_batch(const DictDev &dict, const OmpParams &p, int kmax, int a0mode, int row_cache,
+                            hipStream_t st);
+hipError_t launch_omp_batch_valu(const DictDev &dict, const OmpParams &p, int kmax, int row_cache, hipStream_t st);
+hipError_t launch_omp_batch_mfma(const DictDev &dict, const OmpParams &p, int kmax, int row_cache, hipStream_t st);
+hipError_t launch_omp_batch_bf16(const DictDev &dict, const OmpParams &p, int kmax, int row_cache, hipStream_t st);
+hipError_t launch_omp_refit(const DictDev &dict, const OmpParams &p, hipStream_t st);
+hipError_t launch_omp_multi(const sc_scene *scenes, const int *order, int n, int a0mode, int tile, int row_cache,
+                            int wg_per_cu, int *counter, hipStream_t st);
 hipError_t launch_omp_restricted(const DictDev &dict, const float *D48, const RompParams &p, int kmax,
                                  hipStream_t st);
 hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16_t *W1b, uint16_t *W2b,
@@ -143,7 +150,9 @@ struct sc_dict_s {
     float *D48 = nullptr;   // K x 48 FP32, atoms padded to 16-byte rows
     int *status = nullptr;
     unsigned long long *stats = nullptr;
-    int a0_fp32 = sc::A0_MFMA_F32;   // alpha0 stage of the FP32 encoder (tunable)
+    int a0_fp32 = sc::A0_VALU;       // alpha0 stage of the FP32 encoder (tunable)
+    int row_cache = 0;               // Gram rows kept in registers by the encoder (tunable: 0 or 4)
+    sc::DictDev *ddev = nullptr;     // device copy of `dev`
 };
 
 struct sc_proposer_s {

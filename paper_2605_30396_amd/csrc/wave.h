@@ -51,6 +51,22 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// Unsigned maximum over the wave (wave-uniform result).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, dpp_u<SC_DPP_QP1032>(v));
+    v = max(v, dpp_u<SC_DPP_QP2301>(v));
+    v = max(v, dpp_u<SC_DPP_HMIRROR>(v));
+    v = max(v, dpp_u<SC_DPP_MIRROR>(v));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), e = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(a, b), max(c, e));
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

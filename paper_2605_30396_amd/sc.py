@@ -31,6 +31,7 @@ TRAIN_FP32 = 0x1
 TRAIN_GRAD_ONLY = 0x2
 
 TUNE_FP32_CORRELATION = 1
+TUNE_ROW_CACHE = 2
 CORR_VALU = 0
 CORR_MFMA = 1
 
@@ -51,6 +52,31 @@ P = C.c_void_p
 I32 = C.c_int
 I64 = C.c_int64
 F32 = C.c_float
+
+
+MAX_SCENES = 32
+ORDER_COST = 0
+ORDER_GIVEN = 1
+
+
+class Scene(C.Structure):
+    """sc_scene: one scene of a batched launch."""
+    _fields_ = [("dict", C.c_void_p), ("X", C.c_void_p), ("N", C.c_int64), ("k", C.c_int32), ("eps", C.c_float),
+                ("flags", C.c_int32), ("idx", C.c_void_p), ("coef", C.c_void_p), ("count", C.c_void_p),
+                ("resid", C.c_void_p)]
+
+
+class BatchTuning(C.Structure):
+    """sc_batch_tuning: launch shape of the batched encoder."""
+    _fields_ = [("tile", C.c_int32), ("row_cache", C.c_int32), ("wg_per_cu", C.c_int32), ("order", C.c_int32),
+                ("corr", C.c_int32)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(**{n: int(d[n]) for n, _ in cls._fields_})
 
 
 def load():
@@ -85,6 +111,10 @@ def load():
         "sc_omp_encode_learned": (I32, [P, P, P, I64, I32, F32, I32, I32, P, P, P, P, P, C.c_size_t, P]),
         "sc_omp_encode_restricted": (I32, [P, P, I64, I32, F32, I32, P, I32, P, P, P, P, P, P, P]),
         "sc_omp_encode_rows": (I32, [P, P, P, P, I64, I32, F32, I32, P, P, P, P, P]),
+        "sc_omp_encode_batched_workspace": (C.c_size_t, []),
+        "sc_omp_encode_batched": (I32, [C.POINTER(Scene), I32, C.POINTER(BatchTuning), P, C.c_size_t, P]),
+        "sc_batch_autotune": (I32, [C.POINTER(Scene), I32, I64, P, C.c_size_t, C.POINTER(BatchTuning),
+                                    C.POINTER(F32), P]),
         "sc_proposer_train_workspace": (C.c_size_t, [P, I64]),
         "sc_proposer_train_step": (I32, [P, P, P, I64, P, P, I32, F32, F32, F32, F32, F32, I32, P, P, P,
                                          C.c_size_t, P]),
@@ -104,6 +134,10 @@ def _check(fn, rc):
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _addr(t):
+    return None if t is None else int(t.data_ptr())
 
 
 def _stream(stream):
@@ -281,12 +315,17 @@ def proposer_create(d, H, K, device="cuda:0") -> Proposer:
     return Proposer(h, d, H, K, torch.device(device))
 
 
-def proposer_forward(p: Proposer, X, n_cand=24, want_logits=False, stream=None):
+def proposer_forward(p: Proposer, X, n_cand=24, want_logits=False, cand=None, stream=None):
     """Candidate atoms (N, n_cand) int32 sorted by index (row of -1 = none) and,
-    if asked, the FP32 logits (N, K)."""
+    if asked, the FP32 logits (N, K).  `cand` may be a preallocated output."""
     _dev_f32(X, "X", 2)
     N = X.shape[0]
-    cand = torch.empty((N, n_cand), dtype=torch.int32, device=X.device)
+    if cand is None:
+        cand = torch.empty((N, n_cand), dtype=torch.int32, device=X.device)
+    else:
+        _dev_i32(cand, "cand", 2)
+        if tuple(cand.shape) != (N, n_cand):
+            raise ValueError(f"cand must have shape {(N, n_cand)}")
     logits = torch.empty((N, p.K), dtype=torch.float32, device=X.device) if want_logits else None
     _check("sc_proposer_forward", load().sc_proposer_forward(p.handle, _ptr(X), N, int(n_cand), _ptr(cand),
                                                              _ptr(logits), _stream(stream)))
@@ -369,3 +408,68 @@ def omp_encode_rows(h: Dictionary, X, rows, nrows, max_rows, k, eps, out, flags=
         h.handle, _ptr(X), _ptr(rows), _ptr(nrows), int(max_rows), int(k), float(eps), int(flags), _ptr(idx),
         _ptr(coef), _ptr(count), _ptr(resid), _stream(stream)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# many scenes in one launch
+# ----------------------------------------------------------------------------
+
+def _scene_array(scenes):
+    """scenes: list of dicts {dict: Dictionary, X, k, eps, flags=0, out=(idx, coef, count, resid)}
+    (outputs allocated when absent).  Returns the ctypes array and the list
+    of output tuples."""
+    if not 1 <= len(scenes) <= MAX_SCENES:
+        raise ValueError(f"1..{MAX_SCENES} scenes")
+    arr = (Scene * len(scenes))()
+    outs = []
+    for q, sc_ in enumerate(scenes):
+        X = sc_["X"]
+        _dev_f32(X, "X", 2)
+        N, k = X.shape[0], int(sc_["k"])
+        out = sc_.get("out")
+        if out is None:
+            out = (torch.empty((N, k), dtype=torch.int32, device=X.device),
+                   torch.empty((N, k), dtype=torch.float32, device=X.device),
+                   torch.empty((N,), dtype=torch.int32, device=X.device),
+                   torch.empty((N,), dtype=torch.float32, device=X.device))
+        idx, coef, count, resid = out
+        h = sc_["dict"].handle
+        arr[q] = Scene(h.value if isinstance(h, C.c_void_p) else h, _addr(X), N, k, float(sc_.get("eps", 0.0)),
+                       int(sc_.get("flags", 0)), _addr(idx), _addr(coef), _addr(count), _addr(resid))
+        outs.append(out)
+    return arr, outs
+
+
+def batched_workspace_bytes():
+    return int(load().sc_omp_encode_batched_workspace())
+
+
+def omp_encode_batched(scenes, tuning=None, workspace=None, stream=None):
+    """Encode several scenes (each with its own dictionary, k and eps) in one
+    persistent launch.  tuning: BatchTuning, dict or None.  Returns the list
+    of (idx, coef, count, resid) per scene."""
+    arr, outs = _scene_array(scenes)
+    dev = scenes[0]["X"].device
+    if workspace is None:
+        workspace = torch.empty(batched_workspace_bytes(), dtype=torch.uint8, device=dev)
+    if isinstance(tuning, dict):
+        tuning = BatchTuning.from_dict(tuning)
+    tp = C.byref(tuning) if tuning is not None else None
+    _check("sc_omp_encode_batched", load().sc_omp_encode_batched(arr, len(scenes), tp, _ptr(workspace),
+                                                                 workspace.numel(), _stream(stream)))
+    return outs
+
+
+def batch_autotune(scenes, sample=65536, workspace=None, stream=None):
+    """The library's autotuner for omp_encode_batched on the first `sample`
+    signals of each scene.  Returns (BatchTuning, best time in ms)."""
+    arr, _ = _scene_array(scenes)
+    dev = scenes[0]["X"].device
+    if workspace is None:
+        workspace = torch.empty(batched_workspace_bytes(), dtype=torch.uint8, device=dev)
+    best = BatchTuning()
+    ms = C.c_float(0.0)
+    _check("sc_batch_autotune", load().sc_batch_autotune(arr, len(scenes), int(sample), _ptr(workspace),
+                                                         workspace.numel(), C.byref(best), C.byref(ms),
+                                                         _stream(stream)))
+    return best, float(ms.value)
