@@ -11,7 +11,9 @@ proposer -> top-24 candidates -> restricted Batch-OMP -> full-OMP fallback on
 the signals whose residual exceeds eps), then the radiance of every code at
 one view direction per Gaussian.  Inputs are resident in HBM before timing.
 The comparators (plain FP32 Batch-OMP, BF16 precision form, untrained
-proposer) are timed on the same inputs and reported beside it.
+proposer) are timed on the same inputs and reported beside it, and so is the
+16-scene batch (sizes log-uniform in 50k..6M, K in {128, 256, 512}, k in
+{4, 8, 12, 16}, eps = 0) encoded in one autotuned persistent launch.
 
 Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: this
 build runs on one GPU.
@@ -89,7 +91,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6_000_000)
-    ap.add_argument("--quick", action="store_true", help="headline step only (for profiling)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-scene batched comparator")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline step only, then a 1 GiB device copy (profiling and counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the encoder shards by rows with no exchange, "
@@ -98,6 +102,7 @@ def main():
 
     import torch
 
+    from paper_2605_30396_amd import autotune
     from paper_2605_30396_amd import inputs as I
     from paper_2605_30396_amd import sc, trainer
 
@@ -118,22 +123,9 @@ def main():
     dirg = torch.from_numpy(dirs).to(dev)
     h = sc.gram_precompute(torch.from_numpy(D).to(dev))
 
-    # ---- autotune the FP32 correlation stage on a slice (untimed) ----
-    sl = Xg[:262144]
-    best = None
-    for corr in (sc.CORR_VALU, sc.CORR_MFMA):
-        h.set_tuning(sc.TUNE_FP32_CORRELATION, corr)
-        sc.omp_encode(h, sl, k, eps)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        sc.omp_encode(h, sl, k, eps)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b)
-        if best is None or ms < best[1]:
-            best = (corr, ms)
-    h.set_tuning(sc.TUNE_FP32_CORRELATION, best[0])
+    # ---- autotune the FP32 encoder on a slice (untimed) ----
+    tuned = autotune.tune_dictionary(h, Xg, k, eps, use_cache=False)
+    log(f"encoder tuning {tuned}")
 
     # ---- train the proposer (untimed) ----
     t1 = time.perf_counter()
@@ -143,6 +135,7 @@ def main():
     hist = trainer.train(prop, Xtr_g, sup, cnt, epochs=args.epochs, batch=1024, lr=3e-3, pos_weight=8.0, seed=1)
     train_s = time.perf_counter() - t1
     log(f"proposer trained in {train_s:.1f} s, loss {hist['loss'][-1]:.4f}")
+    del Xtr_g, sup, cnt
     untrained = sc.proposer_create(d, 256, K)
     untrained.set_params(I.mlp_init(I.rng_for(5), d, 256, K))
 
@@ -161,7 +154,7 @@ def main():
         return torch.cuda.Event(enable_timing=True)
 
     def learned_step(p, flags, marks):
-        """The learned encoder as its three kernels (events between them)."""
+        """The learned encoder as its three stages (events between them)."""
         marks[0].record(stream)
         sc.proposer_forward(p, Xg, N_CAND, cand=cand)
         marks[1].record(stream)
@@ -171,24 +164,26 @@ def main():
         sc.omp_encode_rows(h, Xg, miss_rows, miss_count, N, k, eps, out, flags)
         marks[3].record(stream)
 
-    def time_variant(run, nmarks):
-        for _ in range(args.warmup):
+    def time_variant(run, nmarks, steps=None, warmup=None):
+        steps = args.steps if steps is None else steps
+        for _ in range(args.warmup if warmup is None else warmup):
             run([ev() for _ in range(nmarks)])
         torch.cuda.synchronize()
         sc.omp_stats(h, reset=True)
         rec = []
         tw = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             m = [ev() for _ in range(nmarks)]
             run(m)
             rec.append(m)
         torch.cuda.synchronize()
-        wall = (time.perf_counter() - tw) / args.steps
+        wall = (time.perf_counter() - tw) / steps
         st = sc.omp_stats(h)
         phases = [float(np.mean([m[i].elapsed_time(m[i + 1]) for m in rec])) for i in range(nmarks - 1)]
         return wall * 1e3, phases, st
 
     qs = np.random.Generator(np.random.PCG64(11)).choice(N, 4000, replace=False)
+    qsg = torch.from_numpy(qs).to(dev)
     qref = {}
 
     def quality():
@@ -199,8 +194,8 @@ def main():
         import oracle
         if not qref:
             qref.update(oracle.omp(D, X[qs], k, eps))
-        rg = resid[torch.from_numpy(qs).to(dev)].cpu().numpy().astype(np.float64)
-        gi = idx[torch.from_numpy(qs).to(dev)].cpu().numpy()
+        rg = resid[qsg].cpu().numpy().astype(np.float64)
+        gi = idx[qsg].cpu().numpy()
         rr = qref["resid"]
         agg_r = np.sqrt((rr ** 2).sum())
         return dict(resid_gap=float((np.sqrt((rg ** 2).sum()) - agg_r) / agg_r),
@@ -208,73 +203,133 @@ def main():
                     support_mismatch=float(np.mean(np.any(gi != qref["idx"], axis=1))))
 
     results = {}
-    cnt_np = {}
-    # headline: learned (BF16 proposer) + radiance, as one step
-    def headline(marks, p=prop, flags=0):
-        learned_step(p, flags, marks)
+
+    # ---- headline: learned encoder (BF16 proposer) + radiance, one step ----
+    def headline(marks):
+        learned_step(prop, 0, marks)
         sc.sh_eval_sparse(h, idx, coef, count, dirg, sc.DIRS_PER_SIGNAL, out=rgb)
         marks[4].record(stream)
 
-    ms_step, ph, st = time_variant(headline, 5)
+    head_ms_step, ph, st = time_variant(headline, 5)
     results["learned_bf16_proposer"] = dict(ms=sum(ph[:3]), phases_ms=dict(proposer=ph[0], restricted=ph[1],
                                                                           fallback=ph[2]),
                                             fallback_frac=st["fallbacks"] / (N * args.steps), **quality())
     eval_ms = ph[3]
-    head_ms_step = ms_step
     fb_rows = int(miss_count.item())
     cnt_head = count.cpu().numpy()
     miss_np = miss_rows[:fb_rows].cpu().numpy()
-    if not args.quick:
-        for name, flags in (("plain_fp32", 0), ("bf16_precision_form", sc.PREC_BF16)):
-            def run(m, flags=flags):
-                m[0].record(stream)
-                sc.omp_encode(h, Xg, k, eps, flags, out=out)
-                m[1].record(stream)
-            ms, ph2, st2 = time_variant(run, 2)
-            results[name] = dict(ms=ph2[0], **quality())
-            cnt_np[name] = count.cpu().numpy()
-        ms, ph2, st2 = time_variant(lambda m: learned_step(prop, sc.PREC_BF16, m), 4)
-        results["learned_bf16_fallback"] = dict(ms=sum(ph2), phases_ms=dict(proposer=ph2[0], restricted=ph2[1],
-                                                                           fallback=ph2[2]),
-                                                fallback_frac=st2["fallbacks"] / (N * args.steps), **quality())
-        ms, ph2, st2 = time_variant(lambda m: learned_step(untrained, 0, m), 4)
-        results["learned_untrained"] = dict(ms=sum(ph2), phases_ms=dict(proposer=ph2[0], restricted=ph2[1],
+    log(f"headline step {head_ms_step:.2f} ms, phases {ph}")
+    if args.quick:
+        # a plain device copy of known size, for scaling the HBM counters
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"quick": True, "ms_per_step": head_ms_step, "phases_ms": ph, "copy_bytes": 1 << 30}))
+        return
+
+    for name, flags in (("plain_fp32", 0), ("bf16_precision_form", sc.PREC_BF16)):
+        def run(m, flags=flags):
+            m[0].record(stream)
+            sc.omp_encode(h, Xg, k, eps, flags, out=out)
+            m[1].record(stream)
+        _, ph2, st2 = time_variant(run, 2)
+        results[name] = dict(ms=ph2[0], **quality())
+        log(f"{name} {ph2[0]:.2f} ms")
+    _, ph2, st2 = time_variant(lambda m: learned_step(prop, sc.PREC_BF16, m), 4)
+    results["learned_bf16_fallback"] = dict(ms=sum(ph2), phases_ms=dict(proposer=ph2[0], restricted=ph2[1],
                                                                        fallback=ph2[2]),
                                             fallback_frac=st2["fallbacks"] / (N * args.steps), **quality())
-        recall = trainer.support_recall(prop, Xg[:20000], *trainer.omp_labels(h, Xg[:20000], k, eps))
-    else:
-        recall = None
+    _, ph2, st2 = time_variant(lambda m: learned_step(untrained, 0, m), 4)
+    results["learned_untrained"] = dict(ms=sum(ph2), phases_ms=dict(proposer=ph2[0], restricted=ph2[1],
+                                                                   fallback=ph2[2]),
+                                        fallback_frac=st2["fallbacks"] / (N * args.steps), **quality())
+    lab = trainer.omp_labels(h, Xg[:20000], k, eps)
+    recall = trainer.support_recall(prop, Xg[:20000], *lab)
+    recall0 = trainer.support_recall(untrained, Xg[:20000], *lab)
     for v in results.values():
         v["gaussians_per_s"] = round(N / (v["ms"] * 1e-3), 1)
 
-    # ---- roofline of the dominant kernel of the headline step ----
+    # ---- the 16-scene batch in one persistent launch ----
+    batched = None
+    if not args.no_batched:
+        del rgb, dirg
+        torch.cuda.empty_cache()
+        tb = time.perf_counter()
+        specs = I.scene_batch_specs()
+        scenes, hs, data = [], [], []
+        for sp in specs:
+            Ds, Xs = I.scene_inputs(sp)
+            hq = sc.gram_precompute(torch.from_numpy(Ds).to(dev))
+            hs.append(hq)
+            scenes.append(dict(dict=hq, X=torch.from_numpy(Xs).to(dev), k=sp["k"], eps=0.0))
+            data.append((Ds, Xs[:200].copy()))
+            del Xs
+        Nb = sum(sp["N"] for sp in specs)
+        log(f"batched inputs ({Nb} signals) in {time.perf_counter() - tb:.1f} s")
+        tuning, tms = autotune.tune_batched(scenes, sample=65536, use_cache=False)
+        outs = sc.omp_encode_batched(scenes, tuning)
+        for _ in range(args.warmup):
+            sc.omp_encode_batched(scenes, tuning)
+        torch.cuda.synchronize()
+        tms_list = []
+        for _ in range(args.steps):
+            a, b = ev(), ev()
+            a.record(stream)
+            outs = sc.omp_encode_batched(scenes, tuning)
+            b.record(stream)
+            tms_list.append((a, b))
+        torch.cuda.synchronize()
+        bms = float(np.mean([a.elapsed_time(b) for a, b in tms_list]))
+        import oracle
+        gaps = []
+        bflops = 0.0
+        for q, sp in enumerate(specs):
+            Ds, Xq = data[q]
+            ref = oracle.omp(Ds, Xq, sp["k"], 0.0)
+            rg = outs[q][3][:200].cpu().numpy().astype(np.float64)
+            gaps.append(float((np.sqrt((rg ** 2).sum()) - np.sqrt((ref["resid"] ** 2).sum())) /
+                              np.sqrt((ref["resid"] ** 2).sum())))
+            bflops += batch_omp_flops(sp["K"], d, outs[q][2].cpu().numpy())
+        batched = dict(workload="16 scenes, N log-uniform 50k..6M (seed 4), K in {128,256,512}, "
+                                "k in {4,8,12,16}, eps=0, one persistent launch",
+                       N=Nb, ms=round(bms, 3), gaussians_per_s=round(Nb / (bms * 1e-3), 1),
+                       tuning=tuning.as_dict(), tflops=round(bflops / (bms * 1e-3) / 1e12, 3),
+                       max_abs_resid_gap_vs_oracle=round(max(abs(g) for g in gaps), 6))
+        log(f"batched {bms:.2f} ms for {Nb} signals, tuning {tuning.as_dict()}")
+        for hq in hs:
+            hq.destroy()
+        del scenes, outs
+
+    # ---- per-kernel rates of the headline step, roofline of the dominant one ----
     phs = results["learned_bf16_proposer"]["phases_ms"]
-    dom = max(phs, key=phs.get)
-    if dom == "proposer":
-        ach = MLP_FLOPS * N / (phs[dom] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "proposer_topk_kernel<4>", "achieved": round(ach, 3),
-                "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s"}
-        tk = "proposer_topk_kernel"
-        src = kernel_source_hash("proposer.hip", "mfma.h")
-    elif dom == "fallback":
-        fl = batch_omp_flops(K, d, cnt_head[miss_np])
-        ach = fl / (phs[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "omp_batch_kernel<8,12> (fallback rows)", "achieved": round(ach, 3),
-                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s"}
-        tk = "omp_batch_kernel"
-        src = kernel_source_hash("omp_batch.hip")
-    else:
-        ok = np.ones(N, bool)
-        ok[miss_np] = False
-        n = cnt_head[ok].astype(np.float64)
-        fl = float(np.sum(2.0 * N_CAND * d + N_CAND * n * (n + 1)))
-        ach = fl / (phs[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "omp_restricted_kernel<12>", "achieved": round(ach, 3),
-                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s"}
-        tk = "omp_restricted_kernel"
-        src = kernel_source_hash("romp.hip")
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = read_traffic(tk, src)
+    ok = np.ones(N, bool)
+    ok[miss_np] = False
+    n_ok = cnt_head[ok].astype(np.float64)
+    kern = {
+        "proposer": dict(kernel="proposer_topk_kernel", bound="mfma", unit="TFLOP/s", peak=BF16_MFMA_PEAK_TFLOPS,
+                         achieved=MLP_FLOPS * N / (phs["proposer"] * 1e-3) / 1e12,
+                         src=("proposer.hip", "mfma.h")),
+        "restricted": dict(kernel="omp_restricted_kernel", bound="alu", unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS,
+                           achieved=float(np.sum(2.0 * N_CAND * d + N_CAND * n_ok * (n_ok + 1))) /
+                           (phs["restricted"] * 1e-3) / 1e12, src=("romp.hip",)),
+        "fallback": dict(kernel="omp_batch_kernel", bound="alu", unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS,
+                         achieved=batch_omp_flops(K, d, cnt_head[miss_np]) / (phs["fallback"] * 1e-3) / 1e12,
+                         src=("omp_core.h", "omp_batch_impl.h")),
+        "radiance": dict(kernel="sh_eval_kernel", bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
+                         achieved=sh_eval_bytes(N, k) / (eval_ms * 1e-3) / 1e9, src=("sh_eval.hip",)),
+    }
+    for v in kern.values():
+        v["frac"] = round(v["achieved"] / v["peak"], 4)
+        v["achieved"] = round(v["achieved"], 3)
+    dom = max(("proposer", "restricted", "fallback"), key=lambda q: phs[q])
+    kd = kern[dom]
+    roof = {"bound": kd["bound"], "kernel": kd["kernel"], "achieved": kd["achieved"], "peak": kd["peak"],
+            "unit": kd["unit"], "frac": kd["frac"],
+            "traffic": read_traffic(kd["kernel"], kernel_source_hash(*kd["src"]))}
+    per_kernel = {q: {kk: v[kk] for kk in ("kernel", "bound", "achieved", "peak", "unit", "frac")} | {
+        "ms": round(phs[q] if q in phs else eval_ms, 4)} for q, v in kern.items()}
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ----
     cpu = None
@@ -304,17 +359,17 @@ def main():
         "dtype": "bf16+f32",
         "data": "synthetic",
         "config": {"workload": "learned-form: N=6e6 signals d=45, K=512 Gaussian unit-norm dictionary, 4-sparse "
-                               "U[-1,1] + N(0,sigma=1e-3) noise, k=12, eps=1e-2, top-24 candidates; step = learned encode "
-                               "+ one-view radiance",
-                   "N": N, "K": K, "k": k, "eps": eps, "n_cand": N_CAND,
-                   "fp32_correlation": "mfma" if best[0] == sc.CORR_MFMA else "valu"},
+                               "U[-1,1] + N(0,sigma=1e-3) noise, k=12, eps=1e-2, top-24 candidates; step = learned "
+                               "encode + one-view radiance",
+                   "N": N, "K": K, "k": k, "eps": eps, "n_cand": N_CAND, "encoder_tuning": tuned},
         "speedup_vs_plain_fp32": (round(plain["ms"] / results["learned_bf16_proposer"]["ms"], 4) if plain else None),
         "comparators": {k2: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k2, v in results.items()},
-        "radiance": {"ms": round(eval_ms, 4), "GB_per_s": round(sh_eval_bytes(N, k) / (eval_ms * 1e-3) / 1e9, 1),
-                     "hbm_frac": round(sh_eval_bytes(N, k) / (eval_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "batched": batched,
+        "kernels": per_kernel,
         "training": {"seconds": round(train_s, 2), "epochs": args.epochs, "train_N": args.train_N,
-                     "final_loss": round(hist["loss"][-1], 5), "recall_at_24": recall},
+                     "final_loss": round(hist["loss"][-1], 5), "recall_at_24": recall,
+                     "recall_at_24_untrained": recall0},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

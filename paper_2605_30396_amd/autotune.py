@@ -1,0 +1,115 @@
+"""Autotuning of the encoders' launch shapes, with a JSON cache.
+
+* tune_dictionary: times sc_omp_encode on a sample of the caller's signals
+  over {VALU, MFMA} correlation stage x {0, 4} Gram rows in registers (HIP
+  events on the current stream) and sets the fastest on the handle.
+* tune_batched: runs the library's native search (sc_batch_autotune) for
+  the multi-scene launch.
+
+Results are cached per device and problem class in a JSON file
+($SC_TUNE_CACHE, default ~/.cache/paper_2605_30396_amd/tune.json), so a
+second run of the same configuration skips the search.  Tuning changes the
+speed only: the codes are the same up to FP32 rounding order.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import sc
+
+
+def _cache_path():
+    return os.environ.get("SC_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2605_30396_amd", "tune.json"))
+
+
+def _load():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(key, value):
+    data = _load()
+    data[key] = value
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass   # read-only home: the result is still applied, just not kept
+
+
+def _device_name(dev):
+    return torch.cuda.get_device_properties(dev).name
+
+
+def _time(fn, reps=3):
+    fn()
+    st = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def tune_dictionary(h: sc.Dictionary, X, k, eps=0.0, flags=0, sample=262144, use_cache=True):
+    """Pick the fastest correlation stage and row cache of sc_omp_encode for
+    this handle on X[:sample]; returns {"corr", "row_cache", "ms"}."""
+    key = (f"{_device_name(X.device)}|dict|K={h.K}|d={h.d}|k={k}|eps={float(eps):.3g}|flags={int(flags)}"
+           f"|n={min(len(X), sample)}")
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            h.set_tuning(sc.TUNE_FP32_CORRELATION, hit["corr"])
+            h.set_tuning(sc.TUNE_ROW_CACHE, hit["row_cache"])
+            return hit
+    Xs = X[:sample]
+    n = Xs.shape[0]
+    out = (torch.empty((n, k), dtype=torch.int32, device=X.device),
+           torch.empty((n, k), dtype=torch.float32, device=X.device),
+           torch.empty((n,), dtype=torch.int32, device=X.device),
+           torch.empty((n,), dtype=torch.float32, device=X.device))
+    best = None
+    for corr in (sc.CORR_VALU, sc.CORR_MFMA):
+        for rc in (0, 4):
+            h.set_tuning(sc.TUNE_FP32_CORRELATION, corr)
+            h.set_tuning(sc.TUNE_ROW_CACHE, rc)
+            ms = _time(lambda: sc.omp_encode(h, Xs, k, eps, flags, out=out))
+            if best is None or ms < best["ms"]:
+                best = {"corr": corr, "row_cache": rc, "ms": ms}
+    h.set_tuning(sc.TUNE_FP32_CORRELATION, best["corr"])
+    h.set_tuning(sc.TUNE_ROW_CACHE, best["row_cache"])
+    if use_cache:
+        _store(key, best)
+    return best
+
+
+def tune_batched(scenes, sample=65536, use_cache=True):
+    """Launch shape of omp_encode_batched for these scenes (list of dicts as
+    sc.omp_encode_batched takes); returns (BatchTuning, ms)."""
+    dev = scenes[0]["X"].device
+    cls = sorted((s["dict"].K, s["dict"].d, int(s["k"]), round(float(s.get("eps", 0.0)), 6),
+                  int(s.get("flags", 0)), min(int(s["X"].shape[0]), sample)) for s in scenes)
+    key = f"{_device_name(dev)}|batch|{json.dumps(cls)}"
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            return sc.BatchTuning.from_dict(hit["tuning"]), hit["ms"]
+    best, ms = sc.batch_autotune(scenes, sample)
+    if use_cache:
+        _store(key, {"tuning": best.as_dict(), "ms": ms})
+    return best, ms
