@@ -19,7 +19,11 @@ __global__ __launch_bounds__(kOmpThreads) void omp_batch_kernel(DictDev dict, Om
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t s0 = tile * kTileS;
         const int nt = (int)min<int64_t>(kTileS, Nsig - s0);
-        omp_tile<E, KMAX, kTileS, MODE == A0_MFMA_BF16X3, RCQ>(dict, p, MODE, s0, nt, smem_raw, threadIdx.x, tally);
+        // thread-derived addresses are recomputed per tile rather than held
+        // live across the loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        omp_tile<E, KMAX, kTileS, MODE == A0_MFMA_BF16X3, RCQ>(dict, p, MODE, s0, nt, smem_raw, tid, tally);
     }
     if (p.stats && (threadIdx.x & 63) == 0 && tally.sig) {
         atomicAdd(p.stats + 0, tally.sig);

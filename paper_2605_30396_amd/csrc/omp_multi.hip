@@ -93,12 +93,14 @@ __global__ __launch_bounds__(kOmpThreads) void omp_multi_kernel(MultiArgs a) {
         }
         const SceneDesc &sd = a.sc[si];
         const DictDev dict = *sd.dict;
+        int tidv = tid;   // recomputed per tile rather than held live
+        asm volatile("" : "+v"(tidv));
         const OmpParams p = scene_params(sd);
         const int64_t s0 = (tile - sd.tile_begin) * T;
         const int nt = (int)min<int64_t>(T, sd.N - s0);
 #define SC_BODY(EI, EE, KK)                                                                            \
     case 4 * EI + KK / 4 - 1:                                                                          \
-        omp_tile<EE, KK, T, false, RCQ>(dict, p, MODE, s0, nt, smem_raw, tid, tally);                  \
+        omp_tile<EE, KK, T, false, RCQ>(dict, p, MODE, s0, nt, smem_raw, tidv, tally);                 \
         break;
         switch (sd.cls) {
             SC_BODY(0, 1, 4) SC_BODY(0, 1, 8) SC_BODY(0, 1, 12) SC_BODY(0, 1, 16)

@@ -2,24 +2,26 @@
 // (GELU, BF16 weights and activations, FP32 accumulation on MFMA) fused with
 // the exact selection of each signal's n_cand largest logits.
 //
-// Workgroup = 8 waves, tile = 64 signals.  The three layers are computed as
+// Workgroup = 8 waves, tile = 64 signals.  The layers are computed as
 // Z^T = W H^T with v_mfma_f32_32x32x16_bf16: the A operand is a 32 x 16 block
-// of the weight matrix read straight from global memory (L2-resident), the B
-// operand comes from the activation tile in LDS.  Wave w owns N-tile (32
-// signals) w & 1 and the M-tiles (32 outputs) w/2, w/2 + 4, ...; each weight
-// is read once per tile.  In the MFMA output layout a lane holds 16 outputs
-// of one signal, so the selection needs no transpose:
-//   1. each lane takes maxima of groups of 4*KT of its logits: 32 group
+// of the weight matrix read from global memory (L2-resident), the B operand
+// comes from the activation tile in LDS.  Each wave owns whole 32-row blocks
+// of W for both 32-signal halves of the tile, so every weight is read once
+// per tile, and the A operands are prefetched several k-steps ahead.  In the
+// MFMA output layout a lane holds 16 outputs of one signal per block, so the
+// selection needs no transpose:
+//   1. each lane takes maxima of groups of K/32 of its logits: 32 group
 //      maxima per signal;
 //   2. theta = the n_cand-th largest group maximum is a safe lower bound of
 //      the n_cand-th largest logit (n_cand groups reach it);
-//   3. each of the signal's 8 writer lanes appends its logits >= theta to a
-//      private 16-slot list, as keys that order like the logit, with the
-//      atom index in the low bits (unique keys, lower index wins a tie);
-//   4. one wave per signal finds the n_cand-th largest key by a bitwise
-//      search with ballot counts, marks the chosen atoms in a bit mask and
-//      writes them in increasing atom index.
-// A signal whose lists overflow (ties of many logits at the threshold) or
+//   3. each writer lane appends its logits >= theta to a private slot list,
+//      as keys that order like the logit with the atom index in the low bits
+//      (unique keys, lower index wins a tie);
+//   4. eight lanes per signal (eight signals per wave at once) find the
+//      n_cand-th largest key by a bitwise search with group-summed counts,
+//      mark the chosen atoms in a bit mask and write them in increasing atom
+//      index.
+// A signal whose slot lists overflow (many logits tied at the threshold) or
 // whose input is not finite gets candidate list {-1, ...}: the encoder then
 // sends it straight to the full-OMP fallback.  Keys keep the top 32 - IB bits
 // of the order-preserving FP32 key (IB = 7, 8, 9 index bits for K = 128, 256,
@@ -37,8 +39,7 @@ constexpr int kPH = 256;       // hidden width
 constexpr int kXS = 72;        // LDS row stride (bf16) of the input tile
 constexpr int kHS = 264;       // LDS row stride (bf16) of a hidden tile
 constexpr int kNG = 32;        // group maxima per signal
-constexpr int kWriters = 8;    // lanes holding logits of one signal
-constexpr int kSlots = 16;     // candidate slots per writer lane
+constexpr int kSlots = 12;     // candidate slots per writer lane and signal
 
 constexpr int kXBytes = kPT * kXS * 2;        //  9216
 constexpr int kHBytes = kPT * kHS * 2;        // 33792
@@ -63,67 +64,91 @@ __device__ __forceinline__ void sort32_desc(float *v) {
             }
 }
 
+// Sum over the 8 lanes of a group (lanes 8q .. 8q+7).
+__device__ __forceinline__ int grp8_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, SC_DPP_QP1032, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, SC_DPP_QP2301, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, SC_DPP_HMIRROR, 0xF, 0xF, false);
+    return v;
+}
+
 // One hidden layer for the 64-signal tile: Hout = GELU(W Hin^T + b)^T (BF16),
-// 256 outputs; wave w computes N-tile w & 1, M-tiles w/2 and w/2 + 4.
-__device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int ldw, int kin,
+// 256 outputs.  Wave w computes the 32-neuron block w for both signal halves;
+// all KS = kin / 16 A operands of the block are loaded up front.
+template <int KS>
+__device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int ldw,
                                             const float *__restrict__ bias, const uint16_t *__restrict__ Hin, int ldh,
                                             uint16_t *__restrict__ Hout, int wave, int lane) {
-    const int nt = wave & 1, m0 = wave >> 1;
-    floatx16 acc[2] = {floatx16{}, floatx16{}};
     const int lr = lane & 31, lk = 8 * (lane >> 5);
-#pragma unroll 2
-    for (int ks = 0; ks < kin; ks += 16) {
-        const bf16x8 b = ld_bf16x8(Hin + (32 * nt + lr) * ldh + ks + lk);
+    bf16x8 a[KS];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const bf16x8 a = ld_bf16x8(W + (size_t)(32 * (m0 + 4 * q) + lr) * ldw + ks + lk);
-            acc[q] = mfma32(a, b, acc[q]);
+    for (int s = 0; s < KS; ++s) a[s] = ld_bf16x8(W + (size_t)(32 * wave + lr) * ldw + 16 * s + lk);
+    floatx16 acc[2] = {floatx16{}, floatx16{}};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const bf16x8 b = ld_bf16x8(Hin + (32 * n + lr) * ldh + 16 * s + lk);
+            acc[n] = mfma32(a[s], b, acc[n]);
         }
     }
-    const int j = 32 * nt + lr;
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int n = 0; n < 2; ++n) {
+        const int j = 32 * n + lr;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const int i0 = 32 * (m0 + 4 * q) + 8 * g + 4 * (lane >> 5);
+            const int i0 = 32 * wave + 8 * g + 4 * (lane >> 5);
             const float4 bb = *reinterpret_cast<const float4 *>(bias + i0);
-            uint32_t h0 = bf16_bits(gelu_f(acc[q][4 * g + 0] + bb.x));
-            uint32_t h1 = bf16_bits(gelu_f(acc[q][4 * g + 1] + bb.y));
-            uint32_t h2 = bf16_bits(gelu_f(acc[q][4 * g + 2] + bb.z));
-            uint32_t h3 = bf16_bits(gelu_f(acc[q][4 * g + 3] + bb.w));
+            uint32_t h0 = bf16_bits(gelu_f(acc[n][4 * g + 0] + bb.x));
+            uint32_t h1 = bf16_bits(gelu_f(acc[n][4 * g + 1] + bb.y));
+            uint32_t h2 = bf16_bits(gelu_f(acc[n][4 * g + 2] + bb.z));
+            uint32_t h3 = bf16_bits(gelu_f(acc[n][4 * g + 3] + bb.w));
             uint2 pk;
             pk.x = h0 | (h1 << 16);
             pk.y = h2 | (h3 << 16);
             *reinterpret_cast<uint2 *>(Hout + j * kHS + i0) = pk;
         }
+    }
 }
 
 template <int KT>
-__global__ __launch_bounds__(kPThreads) void proposer_topk_kernel(PropDev P, const float *__restrict__ X, int64_t N,
+__global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) void proposer_topk_kernel(PropDev P, const float *__restrict__ X, int64_t N,
                                                                   int n_cand, int32_t *__restrict__ cand,
                                                                   float *__restrict__ logits) {
-    constexpr int K = 128 * KT;     // outputs (= dictionary atoms)
-    constexpr int GS = 4 * KT;      // logits per group maximum
+    constexpr int K = 128 * KT;                 // outputs (= dictionary atoms)
+    constexpr int MT3 = 4 * KT;                 // 32-row blocks of W3
+    constexpr int NPW = MT3 >= kPWaves ? 2 : 1; // signal halves per wave in layer 3
+    constexpr int MPW = MT3 >= kPWaves ? MT3 / kPWaves : 1;   // W3 blocks per wave
+    constexpr int NWR = MT3 >= kPWaves ? 16 : 8;              // writer lanes per signal
+    constexpr int GS = K / kNG;                 // logits per group maximum
+    constexpr int VL = 16 * MPW;                // logits per lane and signal
     constexpr int IB = KT == 1 ? 7 : (KT == 2 ? 8 : 9);   // index bits in a key
     constexpr uint32_t IMASK = (1u << IB) - 1u;
-    constexpr int MW = K / 32;      // mask words per signal
+    constexpr int MW = K / 32;                  // mask words per signal
+    constexpr int WPL = NWR / 8;                // writers handled per selection lane
     extern __shared__ __align__(16) unsigned char lds[];
     uint16_t *Xh = reinterpret_cast<uint16_t *>(lds);
     uint16_t *H1 = reinterpret_cast<uint16_t *>(lds + kXBytes);
     uint16_t *H2 = reinterpret_cast<uint16_t *>(lds + kXBytes + kHBytes);
     int *bad = reinterpret_cast<int *>(lds + kXBytes + 2 * kHBytes);
-    // reused once the first two layers are done (Xh and H1 are dead then)
-    float *gmax = reinterpret_cast<float *>(lds);                            // [64][32]
-    float *theta = gmax + kPT * kNG;                                          // [64]
-    uint32_t *mask = reinterpret_cast<uint32_t *>(theta + kPT);              // [8 waves][16]
-    uint8_t *wcnt = reinterpret_cast<uint8_t *>(mask + kPWaves * 16);        // [64][8]
-    uint32_t *slots = reinterpret_cast<uint32_t *>(wcnt + kPT * kWriters);   // [64][8][16]
+    // reused once layer 3 is done (Xh, H1 and H2 are dead then)
+    float *gmax = reinterpret_cast<float *>(lds);                              // [64][32]
+    float *theta = gmax + kPT * kNG;                                            // [64]
+    uint32_t *mask = reinterpret_cast<uint32_t *>(theta + kPT);                // [64][MW]
+    uint8_t *wcnt = reinterpret_cast<uint8_t *>(mask + kPT * MW);              // [64][NWR]
+    uint32_t *slots = reinterpret_cast<uint32_t *>(wcnt + kPT * NWR);          // [64][NWR][kSlots]
+    static_assert(kPT * kNG * 4 + kPT * 4 + kPT * MW * 4 + kPT * NWR + kPT * NWR * kSlots * 4 <= kPropLds,
+                  "selection scratch must fit in the tile's LDS");
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int d = P.d;
-    const int lr = lane & 31, lk = 8 * (lane >> 5);
     const int64_t ntiles = (N + kPT - 1) / kPT;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // lane-derived addresses are recomputed per tile (cheap) rather than
+        // kept live across the whole loop, which would spill
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int lr = lane & 31, lk = 8 * (lane >> 5);
         const int64_t s0 = tile * kPT;
         const int nt_sig = (int)min<int64_t>(kPT, N - s0);
         __syncthreads();
@@ -159,48 +184,71 @@ __global__ __launch_bounds__(kPThreads) void proposer_topk_kernel(PropDev P, con
             if (q == 0) bad[s] = (s >= nt_sig) || nf;
         }
         __syncthreads();
-        dense_layer(P.W1b, 64, 64, P.b1, Xh, kXS, H1, wave, lane);
+        dense_layer<4>(P.W1b, 64, P.b1, Xh, kXS, H1, wave, lane);
         __syncthreads();
-        dense_layer(P.W2b, kPH, kPH, P.b2, H1, kHS, H2, wave, lane);
+        dense_layer<16>(P.W2b, kPH, P.b2, H1, kHS, H2, wave, lane);
         __syncthreads();
-        // ---- layer 3: logits, N-tile wave & 1, M-tiles wave/2 + 4q ----
-        const int nt = wave & 1, m0 = wave >> 1;
-        const int j = 32 * nt + lr;                 // this lane's signal in the tile
-        const int wr = m0 * 2 + (lane >> 5);        // writer index of the lane for signal j
-        floatx16 acc[KT];
+        // ---- layer 3: logits; wave owns W3 blocks mb(q) for NPW signal halves ----
+        auto mblk = [&](int q) { return MT3 >= kPWaves ? wave + kPWaves * q : (wave & (MT3 - 1)); };
+        const int n0 = MT3 >= kPWaves ? 0 : wave / MT3;   // first signal half of the wave
+        floatx16 acc[MPW][NPW];
 #pragma unroll
-        for (int q = 0; q < KT; ++q) acc[q] = floatx16{};
-#pragma unroll 2
-        for (int ks = 0; ks < kPH; ks += 16) {
-            const bf16x8 b = ld_bf16x8(H2 + j * kHS + ks + lk);
+        for (int q = 0; q < MPW; ++q)
 #pragma unroll
-            for (int q = 0; q < KT; ++q) {
-                const bf16x8 a = ld_bf16x8(P.W3b + (size_t)(32 * (m0 + 4 * q) + lr) * kPH + ks + lk);
-                acc[q] = mfma32(a, b, acc[q]);
-            }
-        }
-        // bias, optional logits, group maxima
+            for (int n = 0; n < NPW; ++n) acc[q][n] = floatx16{};
+        {
+            constexpr int PF = MPW > 1 ? 2 : 4;   // k-steps of A operands in flight
+            bf16x8 a[PF][MPW];
 #pragma unroll
-        for (int q = 0; q < KT; ++q) {
+            for (int s = 0; s < PF; ++s)
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int i0 = 32 * (m0 + 4 * q) + 8 * g + 4 * (lane >> 5);
-                const float4 bb = *reinterpret_cast<const float4 *>(P.b3 + i0);
-                acc[q][4 * g + 0] += bb.x;
-                acc[q][4 * g + 1] += bb.y;
-                acc[q][4 * g + 2] += bb.z;
-                acc[q][4 * g + 3] += bb.w;
-                if (logits && j < nt_sig) {
-                    float4 o = {acc[q][4 * g], acc[q][4 * g + 1], acc[q][4 * g + 2], acc[q][4 * g + 3]};
-                    *reinterpret_cast<float4 *>(logits + (s0 + j) * K + i0) = o;
+                for (int q = 0; q < MPW; ++q)
+                    a[s][q] = ld_bf16x8(P.W3b + (size_t)(32 * mblk(q) + lr) * kPH + 16 * s + lk);
+#pragma unroll
+            for (int s = 0; s < kPH / 16; ++s) {
+#pragma unroll
+                for (int n = 0; n < NPW; ++n) {
+                    const bf16x8 b = ld_bf16x8(H2 + (32 * (n0 + n) + lr) * kHS + 16 * s + lk);
+#pragma unroll
+                    for (int q = 0; q < MPW; ++q) acc[q][n] = mfma32(a[s % PF][q], b, acc[q][n]);
+                }
+                if (s + PF < kPH / 16) {
+#pragma unroll
+                    for (int q = 0; q < MPW; ++q)
+                        a[s % PF][q] = ld_bf16x8(P.W3b + (size_t)(32 * mblk(q) + lr) * kPH + 16 * (s + PF) + lk);
                 }
             }
+        }
+        // writer index of this lane for its signals, and the signals
+        const int wr = (MT3 >= kPWaves ? 2 * wave : 2 * (wave & (MT3 - 1))) + (lane >> 5);
+        // bias, optional logits, group maxima
 #pragma unroll
-            for (int gg = 0; gg < 16 / GS; ++gg) {
-                float mx = acc[q][gg * GS];
+        for (int n = 0; n < NPW; ++n) {
+            const int j = 32 * (n0 + n) + lr;
 #pragma unroll
-                for (int r = 1; r < GS; ++r) mx = fmaxf(mx, acc[q][gg * GS + r]);
-                gmax[j * kNG + (wr * KT + q) * (16 / GS) + gg] = mx;
+            for (int q = 0; q < MPW; ++q) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int i0 = 32 * mblk(q) + 8 * g + 4 * (lane >> 5);
+                    const float4 bb = *reinterpret_cast<const float4 *>(P.b3 + i0);
+                    acc[q][n][4 * g + 0] += bb.x;
+                    acc[q][n][4 * g + 1] += bb.y;
+                    acc[q][n][4 * g + 2] += bb.z;
+                    acc[q][n][4 * g + 3] += bb.w;
+                    if (logits && j < nt_sig) {
+                        float4 o = {acc[q][n][4 * g], acc[q][n][4 * g + 1], acc[q][n][4 * g + 2],
+                                    acc[q][n][4 * g + 3]};
+                        *reinterpret_cast<float4 *>(logits + (s0 + j) * K + i0) = o;
+                    }
+                }
+            }
+            // VL logits of signal j in this lane -> VL / GS group maxima
+#pragma unroll
+            for (int gg = 0; gg < VL / GS; ++gg) {
+                float mx = -__builtin_inff();
+#pragma unroll
+                for (int r = 0; r < GS; ++r) mx = fmaxf(mx, acc[(gg * GS + r) / 16][n][(gg * GS + r) % 16]);
+                gmax[j * kNG + wr * (VL / GS) + gg] = mx;
             }
         }
         __syncthreads();
@@ -218,70 +266,92 @@ __global__ __launch_bounds__(kPThreads) void proposer_topk_kernel(PropDev P, con
         }
         __syncthreads();
         // ---- candidates above the threshold, into private slots ----
-        {
+#pragma unroll
+        for (int n = 0; n < NPW; ++n) {
+            const int j = 32 * (n0 + n) + lr;
             const float th = theta[j];
-            uint32_t *myslots = slots + (j * kWriters + wr) * kSlots;
+            uint32_t *myslots = slots + (j * NWR + wr) * kSlots;
             int cnt = 0;
 #pragma unroll
-            for (int q = 0; q < KT; ++q)
+            for (int q = 0; q < MPW; ++q)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const float z = acc[q][r];
+                    const float z = acc[q][n][r];
                     if (z >= th) {
-                        const int i = 32 * (m0 + 4 * q) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        const int i = 32 * mblk(q) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                         if (cnt < kSlots) myslots[cnt] = (order_key(z) & ~IMASK) | (IMASK - (uint32_t)i);
                         ++cnt;
                     }
                 }
-            wcnt[j * kWriters + wr] = (uint8_t)min(cnt, 255);
+            wcnt[j * NWR + wr] = (uint8_t)min(cnt, 255);
         }
         __syncthreads();
-        // ---- exact top-n_cand per signal (one wave per signal) ----
-        for (int s = wave; s < nt_sig; s += kPWaves) {
-            int32_t *out = cand + (s0 + s) * n_cand;
-            int wc = lane < kWriters ? (int)wcnt[s * kWriters + lane] : 0;
-            const bool over = __ballot(lane < kWriters && wc > kSlots) != 0;
-            // lane i takes slots i and i + 64 (writer = slot / 16)
-            uint32_t k0 = 0, k1 = 0;
-            {
-                const int q0 = lane, q1 = lane + 64;
-                const int c0 = wcnt[s * kWriters + (q0 >> 4)], c1 = wcnt[s * kWriters + (q1 >> 4)];
-                if ((q0 & 15) < c0 && (q0 & 15) < kSlots) k0 = slots[s * kWriters * kSlots + q0];
-                if ((q1 & 15) < c1 && (q1 & 15) < kSlots) k1 = slots[s * kWriters * kSlots + q1];
+        // ---- exact top-n_cand: 8 lanes per signal, 8 signals per wave ----
+        {
+            const int g = lane & 7, s = 8 * wave + (lane >> 3);
+            uint32_t key[WPL * kSlots];
+            int over = 0, have = 0;
+            uint32_t lim[WPL];   // wave-wide bound on the filled slots of writer block w
+#pragma unroll
+            for (int w = 0; w < WPL; ++w) {
+                const int wrq = g + 8 * w;
+                const int c = wcnt[s * NWR + wrq];
+                over |= c > kSlots;
+                have += min(c, kSlots);
+                lim[w] = wave_max_u32((uint32_t)min(c, kSlots));
+#pragma unroll
+                for (int e = 0; e < kSlots; ++e)
+                    key[w * kSlots + e] = e < c ? slots[(s * NWR + wrq) * kSlots + e] : 0u;
             }
-            const int total = __popcll(__ballot(k0 != 0)) + __popcll(__ballot(k1 != 0));
-            if (bad[s] || over || total < n_cand) {
-                if (lane < n_cand) out[lane] = -1;
-                continue;
-            }
+            over = grp8_sum(over);
+            have = grp8_sum(have);
+            const bool skip = s >= nt_sig || bad[s] || over || have < n_cand;
             // largest tau with #{key >= tau} >= n_cand: the n_cand-th largest key
+            // (empty slots hold 0, which no t2 >= 1 counts)
             uint32_t tau = 0;
             for (int bit = 31; bit >= 0; --bit) {
                 const uint32_t t2 = tau | (1u << bit);
-                const int c = __popcll(__ballot(k0 >= t2)) + __popcll(__ballot(k1 >= t2));
-                if (c >= n_cand) tau = t2;
+                int c = 0;
+#pragma unroll
+                for (int w = 0; w < WPL; ++w)
+#pragma unroll
+                    for (int e = 0; e < kSlots; ++e)
+                        if ((uint32_t)e < lim[w]) c += key[w * kSlots + e] >= t2 ? 1 : 0;
+                c = grp8_sum(c);
+                tau = c >= n_cand ? t2 : tau;
             }
             // mark the chosen atoms, then list them in increasing index
-            uint32_t *mw = mask + wave * 16;
-            if (lane < MW) mw[lane] = 0u;
+            uint32_t *mw = mask + s * MW;
+            for (int w = g; w < MW; w += 8) mw[w] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            if (k0 >= tau && k0 != 0) {
-                const uint32_t i = IMASK - (k0 & IMASK);
-                atomicOr(&mw[i >> 5], 1u << (i & 31));
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (!skip) {
+#pragma unroll
+                for (int e = 0; e < WPL * kSlots; ++e)
+                    if (key[e] >= tau && key[e] != 0u) {
+                        const uint32_t i = IMASK - (key[e] & IMASK);
+                        atomicOr(&mw[i >> 5], 1u << (i & 31));
+                    }
             }
-            if (k1 >= tau && k1 != 0) {
-                const uint32_t i = IMASK - (k1 & IMASK);
-                atomicOr(&mw[i >> 5], 1u << (i & 31));
-            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            if (lane < MW) {
-                uint32_t word = mw[lane];
-                int pos = 0;
-                for (int v = 0; v < lane; ++v) pos += __popc(mw[v]);
-                while (word) {
-                    const int bpos = __ffs(word) - 1;
-                    out[pos++] = 32 * lane + bpos;
-                    word &= word - 1u;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (s < nt_sig) {
+                int32_t *out = cand + (s0 + s) * n_cand;
+                if (skip) {
+                    for (int t = g; t < n_cand; t += 8) out[t] = -1;
+                } else {
+                    for (int w = g; w < MW; w += 8) {
+                        int pos = 0;
+                        for (int v = 0; v < w; ++v) pos += __popc(mw[v]);
+                        uint32_t word = mw[w];
+                        while (word) {
+                            const int bpos = __ffs(word) - 1;
+                            out[pos++] = 32 * w + bpos;
+                            word &= word - 1u;
+                        }
+                    }
                 }
             }
         }
