@@ -138,6 +138,9 @@ def main():
     del Xtr_g, sup, cnt
     untrained = sc.proposer_create(d, 256, K)
     untrained.set_params(I.mlp_init(I.rng_for(5), d, 256, K))
+    # restricted-step cap of the learned encoder (untimed)
+    tuned_learned = autotune.tune_learned(h, prop, Xg, k, eps, use_cache=False)
+    log(f"learned tuning {tuned_learned}")
 
     # ---- buffers ----
     idx = torch.empty((N, k), dtype=torch.int32, device=dev)
@@ -154,9 +157,13 @@ def main():
         return torch.cuda.Event(enable_timing=True)
 
     def learned_step(p, flags, marks):
-        """The learned encoder as its three stages (events between them)."""
+        """The learned encoder as its three stages (events between them);
+        p = None: correlation screening in place of the network."""
         marks[0].record(stream)
-        sc.proposer_forward(p, Xg, N_CAND, cand=cand)
+        if p is None:
+            sc.screen_topk(h, Xg, N_CAND, cand=cand)
+        else:
+            sc.proposer_forward(p, Xg, N_CAND, cand=cand)
         marks[1].record(stream)
         sc.omp_encode_restricted(h, Xg, k, eps, cand, flags & ~sc.PREC_BF16, out=out, miss_rows=miss_rows,
                                  miss_count=miss_count)
@@ -245,9 +252,16 @@ def main():
     results["learned_untrained"] = dict(ms=sum(ph2), phases_ms=dict(proposer=ph2[0], restricted=ph2[1],
                                                                    fallback=ph2[2]),
                                         fallback_frac=st2["fallbacks"] / (N * args.steps), **quality())
+    _, ph2, st2 = time_variant(lambda m: learned_step(None, 0, m), 4)
+    results["screened_top24"] = dict(ms=sum(ph2), phases_ms=dict(screen=ph2[0], restricted=ph2[1],
+                                                                fallback=ph2[2]),
+                                     fallback_frac=st2["fallbacks"] / (N * args.steps), **quality())
     lab = trainer.omp_labels(h, Xg[:20000], k, eps)
     recall = trainer.support_recall(prop, Xg[:20000], *lab)
     recall0 = trainer.support_recall(untrained, Xg[:20000], *lab)
+    scr = sc.screen_topk(h, Xg[:20000], N_CAND).cpu().numpy()
+    li, lc = (t.cpu().numpy() for t in lab)
+    recall_screen = float(np.mean([set(li[i, :max(lc[i], 0)]) <= set(scr[i]) for i in range(len(scr))]))
     for v in results.values():
         v["gaussians_per_s"] = round(N / (v["ms"] * 1e-3), 1)
 
@@ -361,7 +375,8 @@ def main():
         "config": {"workload": "learned-form: N=6e6 signals d=45, K=512 Gaussian unit-norm dictionary, 4-sparse "
                                "U[-1,1] + N(0,sigma=1e-3) noise, k=12, eps=1e-2, top-24 candidates; step = learned "
                                "encode + one-view radiance",
-                   "N": N, "K": K, "k": k, "eps": eps, "n_cand": N_CAND, "encoder_tuning": tuned},
+                   "N": N, "K": K, "k": k, "eps": eps, "n_cand": N_CAND, "encoder_tuning": tuned,
+                   "learned_tuning": tuned_learned},
         "speedup_vs_plain_fp32": (round(plain["ms"] / results["learned_bf16_proposer"]["ms"], 4) if plain else None),
         "comparators": {k2: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k2, v in results.items()},
@@ -369,7 +384,7 @@ def main():
         "kernels": per_kernel,
         "training": {"seconds": round(train_s, 2), "epochs": args.epochs, "train_N": args.train_N,
                      "final_loss": round(hist["loss"][-1], 5), "recall_at_24": recall,
-                     "recall_at_24_untrained": recall0},
+                     "recall_at_24_untrained": recall0, "recall_at_24_screening": recall_screen},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

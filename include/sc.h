@@ -143,11 +143,18 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
  *     a tile of 16 signals: SC_CORR_VALU (FP32 FMAs, default) or SC_CORR_MFMA
  *     (FP32 matrix cores).
  *   SC_TUNE_ROW_CACHE  Gram rows of the first selected atoms kept in
- *     registers by the encoder: 0 (every row re-read from cache memory when
- *     the correlations are formed) or 4 (default; applies to K <= 512).
+ *     registers by the encoder: 0 (default for K > 256: every row re-read
+ *     from cache memory when the correlations are formed) or 4 (applies to
+ *     K <= 512).
+ *   SC_TUNE_RESTRICTED_CAP  at most this many restricted-OMP steps in
+ *     sc_omp_encode_learned / _restricted (0 = k, default).  A signal whose
+ *     candidate code is still above eps after the cap goes to the full-OMP
+ *     fallback, so every code still meets the tolerance; only the split of
+ *     signals between the two paths (and the speed) changes.
  */
 #define SC_TUNE_FP32_CORRELATION 1
 #define SC_TUNE_ROW_CACHE 2
+#define SC_TUNE_RESTRICTED_CAP 3
 #define SC_CORR_VALU 0
 #define SC_CORR_MFMA 1
 int sc_dict_set_tuning(sc_dict h, int key, int value);
@@ -258,6 +265,20 @@ size_t sc_omp_encode_learned_workspace(int64_t N, int n_cand);
 int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, int k, float eps, int flags,
                           int n_cand, int32_t *idx, float *coef, int32_t *count, float *resid, void *workspace,
                           size_t ws_bytes, void *stream);
+
+/*
+ * sc_screen_topk -- correlation screening, the proposer-free baseline of the
+ * learned encoder: for each signal the n_cand atoms of largest |<a_j, x>|
+ * (one BF16 MFMA product with the dictionary, FP32 accumulation; exact
+ * top-n_cand of those values, ties to the lower index), written as sc_
+ * proposer_forward writes them (sorted by atom index, -1 row for a signal
+ * that is not finite).  Feed the list to sc_omp_encode_restricted and
+ * sc_omp_encode_rows to run the screened encoder.
+ *   K in {128, 256, 512}, d <= 64, 1 <= n_cand <= min(32, K)
+ *   cand  device N x n_cand int32 (out)
+ * Errors: SC_EINVAL, SC_EDEVICE.
+ */
+int sc_screen_topk(sc_dict h, const float *X, int64_t N, int n_cand, int32_t *cand, void *stream);
 
 /*
  * sc_omp_encode_restricted -- step 2 and 3 of sc_omp_encode_learned on their

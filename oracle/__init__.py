@@ -27,6 +27,7 @@ from .mlp import (  # noqa: F401
     bce_with_logits,
     adam_step,
     topk_lowest_index,
+    bf16_round,
     multi_hot,
 )
 from .learned import learned_encode  # noqa: F401

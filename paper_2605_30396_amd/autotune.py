@@ -5,11 +5,14 @@
   events on the current stream) and sets the fastest on the handle.
 * tune_batched: runs the library's native search (sc_batch_autotune) for
   the multi-scene launch.
+* tune_learned: picks the restricted-OMP step cap of the learned encoder.
 
 Results are cached per device and problem class in a JSON file
 ($SC_TUNE_CACHE, default ~/.cache/paper_2605_30396_amd/tune.json), so a
-second run of the same configuration skips the search.  Tuning changes the
-speed only: the codes are the same up to FP32 rounding order.
+second run of the same configuration skips the search.  The first two change
+the speed only (the codes are the same up to FP32 rounding order); the cap
+of the learned encoder also moves signals between its restricted and
+full-OMP paths, with every code inside the same tolerance.
 """
 from __future__ import annotations
 
@@ -113,3 +116,37 @@ def tune_batched(scenes, sample=65536, use_cache=True):
     if use_cache:
         _store(key, {"tuning": best.as_dict(), "ms": ms})
     return best, ms
+
+
+def tune_learned(h: sc.Dictionary, p: sc.Proposer, X, k, eps, flags=0, n_cand=24, sample=1 << 20,
+                 caps=(0, 8, 6, 5, 4), use_cache=True):
+    """Pick the restricted-OMP step cap of sc_omp_encode_learned (0 = k) that
+    makes the whole learned encode fastest on X[:sample]; every choice meets
+    the same tolerance (signals past the cap take the full-OMP fallback).
+    Returns {"restricted_cap", "ms"}."""
+    key = (f"{_device_name(X.device)}|learned|K={h.K}|d={h.d}|k={k}|eps={float(eps):.3g}|flags={int(flags)}"
+           f"|n_cand={n_cand}|n={min(len(X), sample)}")
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            h.set_tuning(sc.TUNE_RESTRICTED_CAP, hit["restricted_cap"])
+            return hit
+    Xs = X[:sample]
+    n = Xs.shape[0]
+    out = (torch.empty((n, k), dtype=torch.int32, device=X.device),
+           torch.empty((n, k), dtype=torch.float32, device=X.device),
+           torch.empty((n,), dtype=torch.int32, device=X.device),
+           torch.empty((n,), dtype=torch.float32, device=X.device))
+    ws = torch.empty(sc.learned_workspace_bytes(n, n_cand), dtype=torch.uint8, device=X.device)
+    best = None
+    for cap in caps:
+        if cap > k:
+            continue
+        h.set_tuning(sc.TUNE_RESTRICTED_CAP, cap)
+        ms = _time(lambda: sc.omp_encode_learned(h, p, Xs, k, eps, n_cand, flags, out=out, workspace=ws))
+        if best is None or ms < best["ms"]:
+            best = {"restricted_cap": cap, "ms": ms}
+    h.set_tuning(sc.TUNE_RESTRICTED_CAP, best["restricted_cap"])
+    if use_cache:
+        _store(key, best)
+    return best

@@ -419,25 +419,28 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
     __syncthreads();   // the previous tile is done with Xt and A0
     load_tile<T>(p, dict.d, s0, nt, Xt, tid);
     __syncthreads();
-    bool split = false;
-    if (mode == A0_MFMA_F32) {
-        alpha0_mfma_f32<E, T>(dict.DT, dict.d, Xt, A0, wave, lane);
-    } else if (kSplitOK && T == 16 && mode == A0_MFMA_BF16X3) {
-        uint16_t *Xh = reinterpret_cast<uint16_t *>(Xt + 64 * T);
-        uint16_t *Xl = Xh + T * kXhs;
-        for (int q = tid; q < T * 64; q += kOmpThreads) {
-            const int s = q >> 6, f = q & 63;
-            const float v = Xt[f * T + s];
-            const uint16_t hi = bf16_bits(v);
-            Xh[s * kXhs + f] = hi;
-            Xl[s * kXhs + f] = bf16_bits(v - bf16_to_f32(hi));
+    bool split = false, done = false;
+    if constexpr (T % 16 == 0) {   // the MFMA stages work on 16-signal column blocks
+        if (mode == A0_MFMA_F32) {
+            alpha0_mfma_f32<E, T>(dict.DT, dict.d, Xt, A0, wave, lane);
+            done = true;
+        } else if (kSplitOK && T == 16 && mode == A0_MFMA_BF16X3) {
+            uint16_t *Xh = reinterpret_cast<uint16_t *>(Xt + 64 * T);
+            uint16_t *Xl = Xh + T * kXhs;
+            for (int q = tid; q < T * 64; q += kOmpThreads) {
+                const int s = q >> 6, f = q & 63;
+                const float v = Xt[f * T + s];
+                const uint16_t hi = bf16_bits(v);
+                Xh[s * kXhs + f] = hi;
+                Xl[s * kXhs + f] = bf16_bits(v - bf16_to_f32(hi));
+            }
+            __syncthreads();
+            alpha0_mfma_bf16x3<E>(dict.Dbf, dict.Dlo, Xh, Xl, A0, wave, lane);
+            split = true;
+            done = true;
         }
-        __syncthreads();
-        alpha0_mfma_bf16x3<E>(dict.Dbf, dict.Dlo, Xh, Xl, A0, wave, lane);
-        split = true;
-    } else {
-        alpha0_valu<E, T>(dict.DT, dict.d, Xt, A0, tid);
     }
+    if (!done) alpha0_valu<E, T>(dict.DT, dict.d, Xt, A0, tid);
     __syncthreads();
     for (int s = wave; s < nt; s += kOmpWaves) {
         const int64_t sig = p.rows ? (int64_t)p.rows[s0 + s] : s0 + s;

@@ -39,7 +39,6 @@ constexpr int kPH = 256;       // hidden width
 constexpr int kXS = 72;        // LDS row stride (bf16) of the input tile
 constexpr int kHS = 264;       // LDS row stride (bf16) of a hidden tile
 constexpr int kNG = 32;        // group maxima per signal
-constexpr int kSlots = 12;     // candidate slots per writer lane and signal
 
 constexpr int kXBytes = kPT * kXS * 2;        //  9216
 constexpr int kHBytes = kPT * kHS * 2;        // 33792
@@ -111,10 +110,12 @@ __device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int 
     }
 }
 
-template <int KT>
-__global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) void proposer_topk_kernel(PropDev P, const float *__restrict__ X, int64_t N,
-                                                                  int n_cand, int32_t *__restrict__ cand,
-                                                                  float *__restrict__ logits) {
+// SCREEN: correlation screening instead of the MLP -- the "logits" are
+// |D^T x / ||x|||| from one BF16 MFMA layer with W3 = bf16(D) (K x 64).
+template <int KT, bool SCREEN>
+__global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) void proposer_topk_kernel(
+    PropDev P, const float *__restrict__ X, int64_t N, int n_cand, int32_t *__restrict__ cand,
+    float *__restrict__ logits) {
     constexpr int K = 128 * KT;                 // outputs (= dictionary atoms)
     constexpr int MT3 = 4 * KT;                 // 32-row blocks of W3
     constexpr int NPW = MT3 >= kPWaves ? 2 : 1; // signal halves per wave in layer 3
@@ -126,18 +127,23 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     constexpr uint32_t IMASK = (1u << IB) - 1u;
     constexpr int MW = K / 32;                  // mask words per signal
     constexpr int WPL = NWR / 8;                // writers handled per selection lane
+    constexpr int kSlots = VL < 16 ? VL : 16;   // candidate slots per writer lane and signal
+                                                // (= VL for K <= 256: no overflow possible)
     extern __shared__ __align__(16) unsigned char lds[];
     uint16_t *Xh = reinterpret_cast<uint16_t *>(lds);
     uint16_t *H1 = reinterpret_cast<uint16_t *>(lds + kXBytes);
     uint16_t *H2 = reinterpret_cast<uint16_t *>(lds + kXBytes + kHBytes);
     int *bad = reinterpret_cast<int *>(lds + kXBytes + 2 * kHBytes);
-    // reused once layer 3 is done (Xh, H1 and H2 are dead then)
-    float *gmax = reinterpret_cast<float *>(lds);                              // [64][32]
-    float *theta = gmax + kPT * kNG;                                            // [64]
+    // reused once layer 3 is done (Xh, H1 and H2 are dead then); the group
+    // maxima are dead once theta is known, so the slots overlay them
+    float *theta = reinterpret_cast<float *>(lds);                              // [64]
     uint32_t *mask = reinterpret_cast<uint32_t *>(theta + kPT);                // [64][MW]
     uint8_t *wcnt = reinterpret_cast<uint8_t *>(mask + kPT * MW);              // [64][NWR]
-    uint32_t *slots = reinterpret_cast<uint32_t *>(wcnt + kPT * NWR);          // [64][NWR][kSlots]
-    static_assert(kPT * kNG * 4 + kPT * 4 + kPT * MW * 4 + kPT * NWR + kPT * NWR * kSlots * 4 <= kPropLds,
+    float *gmax = reinterpret_cast<float *>(wcnt + kPT * NWR);                 // [64][32]
+    uint32_t *slots = reinterpret_cast<uint32_t *>(gmax);                      // [64][NWR][kSlots]
+    static_assert(kPT * 4 + kPT * MW * 4 + kPT * NWR +
+                          (kPT * kNG * 4 > kPT * NWR * kSlots * 4 ? kPT * kNG * 4 : kPT * NWR * kSlots * 4) <=
+                      kPropLds,
                   "selection scratch must fit in the tile's LDS");
 
     const int d = P.d;
@@ -184,10 +190,16 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             if (q == 0) bad[s] = (s >= nt_sig) || nf;
         }
         __syncthreads();
-        dense_layer<4>(P.W1b, 64, P.b1, Xh, kXS, H1, wave, lane);
-        __syncthreads();
-        dense_layer<16>(P.W2b, kPH, P.b2, H1, kHS, H2, wave, lane);
-        __syncthreads();
+        if constexpr (!SCREEN) {
+            dense_layer<4>(P.W1b, 64, P.b1, Xh, kXS, H1, wave, lane);
+            __syncthreads();
+            dense_layer<16>(P.W2b, kPH, P.b2, H1, kHS, H2, wave, lane);
+            __syncthreads();
+        }
+        // layer-3 input: the second hidden tile, or the signal tile when screening
+        constexpr int KIN = SCREEN ? 64 : kPH;
+        const uint16_t *Hin = SCREEN ? Xh : H2;
+        constexpr int LDH = SCREEN ? kXS : kHS;
         // ---- layer 3: logits; wave owns W3 blocks mb(q) for NPW signal halves ----
         auto mblk = [&](int q) { return MT3 >= kPWaves ? wave + kPWaves * q : (wave & (MT3 - 1)); };
         const int n0 = MT3 >= kPWaves ? 0 : wave / MT3;   // first signal half of the wave
@@ -203,22 +215,23 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             for (int s = 0; s < PF; ++s)
 #pragma unroll
                 for (int q = 0; q < MPW; ++q)
-                    a[s][q] = ld_bf16x8(P.W3b + (size_t)(32 * mblk(q) + lr) * kPH + 16 * s + lk);
+                    a[s][q] = ld_bf16x8(P.W3b + (size_t)(32 * mblk(q) + lr) * KIN + 16 * s + lk);
 #pragma unroll
-            for (int s = 0; s < kPH / 16; ++s) {
+            for (int s = 0; s < KIN / 16; ++s) {
 #pragma unroll
                 for (int n = 0; n < NPW; ++n) {
-                    const bf16x8 b = ld_bf16x8(H2 + (32 * (n0 + n) + lr) * kHS + 16 * s + lk);
+                    const bf16x8 b = ld_bf16x8(Hin + (32 * (n0 + n) + lr) * LDH + 16 * s + lk);
 #pragma unroll
                     for (int q = 0; q < MPW; ++q) acc[q][n] = mfma32(a[s % PF][q], b, acc[q][n]);
                 }
-                if (s + PF < kPH / 16) {
+                if (s + PF < KIN / 16) {
 #pragma unroll
                     for (int q = 0; q < MPW; ++q)
-                        a[s % PF][q] = ld_bf16x8(P.W3b + (size_t)(32 * mblk(q) + lr) * kPH + 16 * (s + PF) + lk);
+                        a[s % PF][q] = ld_bf16x8(P.W3b + (size_t)(32 * mblk(q) + lr) * KIN + 16 * (s + PF) + lk);
                 }
             }
         }
+        __syncthreads();   // every wave is done reading the layer-3 input before the scratch overlays it
         // writer index of this lane for its signals, and the signals
         const int wr = (MT3 >= kPWaves ? 2 * wave : 2 * (wave & (MT3 - 1))) + (lane >> 5);
         // bias, optional logits, group maxima
@@ -230,11 +243,16 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int i0 = 32 * mblk(q) + 8 * g + 4 * (lane >> 5);
-                    const float4 bb = *reinterpret_cast<const float4 *>(P.b3 + i0);
-                    acc[q][n][4 * g + 0] += bb.x;
-                    acc[q][n][4 * g + 1] += bb.y;
-                    acc[q][n][4 * g + 2] += bb.z;
-                    acc[q][n][4 * g + 3] += bb.w;
+                    if constexpr (SCREEN) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[q][n][4 * g + r] = fabsf(acc[q][n][4 * g + r]);
+                    } else {
+                        const float4 bb = *reinterpret_cast<const float4 *>(P.b3 + i0);
+                        acc[q][n][4 * g + 0] += bb.x;
+                        acc[q][n][4 * g + 1] += bb.y;
+                        acc[q][n][4 * g + 2] += bb.z;
+                        acc[q][n][4 * g + 3] += bb.w;
+                    }
                     if (logits && j < nt_sig) {
                         float4 o = {acc[q][n][4 * g], acc[q][n][4 * g + 1], acc[q][n][4 * g + 2],
                                     acc[q][n][4 * g + 3]};
@@ -384,10 +402,10 @@ hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16
     return hipGetLastError();
 }
 
-template <int KT>
+template <int KT, bool SCREEN>
 static hipError_t launch_topk_t(const PropDev &P, const float *X, int64_t N, int n_cand, int32_t *cand,
                                 float *logits, hipStream_t st) {
-    auto kern = proposer_topk_kernel<KT>;
+    auto kern = proposer_topk_kernel<KT, SCREEN>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kPropLds);
@@ -407,9 +425,23 @@ hipError_t launch_proposer_topk(const PropDev &P, const float *X, int64_t N, int
                                 float *logits, hipStream_t st) {
     if (P.H != kPH || P.d > 64 || n_cand < 1 || n_cand > kNG) return hipErrorInvalidValue;
     switch (P.K) {
-        case 128: return launch_topk_t<1>(P, X, N, n_cand, cand, logits, st);
-        case 256: return launch_topk_t<2>(P, X, N, n_cand, cand, logits, st);
-        case 512: return launch_topk_t<4>(P, X, N, n_cand, cand, logits, st);
+        case 128: return launch_topk_t<1, false>(P, X, N, n_cand, cand, logits, st);
+        case 256: return launch_topk_t<2, false>(P, X, N, n_cand, cand, logits, st);
+        case 512: return launch_topk_t<4, false>(P, X, N, n_cand, cand, logits, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Correlation screening: the n_cand atoms of largest |<a_j, x>| by one BF16
+// MFMA product with the dictionary's BF16 copy Dbf (Kp x 64, features padded).
+hipError_t launch_screen_topk(const uint16_t *Dbf, int d, int K, const float *X, int64_t N, int n_cand,
+                              int32_t *cand, hipStream_t st) {
+    if (d > 64 || n_cand < 1 || n_cand > kNG) return hipErrorInvalidValue;
+    PropDev P{d, kPH, K, nullptr, nullptr, nullptr, nullptr, Dbf, nullptr};
+    switch (K) {
+        case 128: return launch_topk_t<1, true>(P, X, N, n_cand, cand, nullptr, st);
+        case 256: return launch_topk_t<2, true>(P, X, N, n_cand, cand, nullptr, st);
+        case 512: return launch_topk_t<4, true>(P, X, N, n_cand, cand, nullptr, st);
         default: return hipErrorInvalidValue;
     }
 }

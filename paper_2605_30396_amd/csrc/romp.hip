@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
 #pragma unroll
         for (int it = 0; it < KMAX; ++it) {
             if (active) {
-                bool go = it < k;
+                bool go = it < p.kcap;
                 if (go && eps2 > 0.f) {
                     if (rr <= eps2 - band) {
                         go = false;
@@ -258,9 +258,12 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
         __builtin_amdgcn_wave_barrier();
 
         // ---- finalise ----
-        grp_back_substitute<KMAX>(gs, n, g);
+        // A code whose tracked ||r||^2 is clearly above eps^2 (beyond the FP32
+        // band) is a miss: no coefficients or explicit residual are needed.
         const bool ok_sig = valid && !nf && cand_ok;
-        bool want_refit = ok_sig && n > 0 && p.fp64_refit && (lmax / lmin) * (lmax / lmin) > p.kappa_max;
+        const bool need = ok_sig && (explicit_done || xx == 0.f || rr <= eps2 + band);
+        if (__ballot(need) != 0) grp_back_substitute<KMAX>(gs, n, g);
+        bool want_refit = need && n > 0 && p.fp64_refit && (lmax / lmin) * (lmax / lmin) > p.kappa_max;
         // FP64 refits, one group at a time (rare)
         uint64_t rb = __ballot(want_refit && g == 0);
         while (rb) {
@@ -307,8 +310,10 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
             explicit_done = false;
             if (g == 0) n_refit += 1;
         }
-        float re = grp_resid2<KMAX>(gs, n, D48, d, g);
+        float re = 3.4e38f;
+        if (__ballot(need && !explicit_done) != 0) re = grp_resid2<KMAX>(gs, need ? n : 0, D48, d, g);
         if (explicit_done) re = rr_expl;
+        if (!need) re = 3.4e38f;
         if (valid) {
             int32_t *oidx = p.idx + sig * k;
             float *ocoef = p.coef + sig * k;

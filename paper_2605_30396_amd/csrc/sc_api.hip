@@ -196,6 +196,11 @@ int sc_dict_set_tuning(sc_dict h, int key, int value) {
         h->row_cache = value;
         return SC_OK;
     }
+    if (key == SC_TUNE_RESTRICTED_CAP) {
+        if (value < 0 || value > 32) return SC_EINVAL;
+        h->restricted_cap = value;
+        return SC_OK;
+    }
     return SC_EINVAL;
 }
 
@@ -207,6 +212,10 @@ int sc_dict_get_tuning(sc_dict h, int key, int *value) {
     }
     if (key == SC_TUNE_ROW_CACHE) {
         *value = h->row_cache;
+        return SC_OK;
+    }
+    if (key == SC_TUNE_RESTRICTED_CAP) {
+        *value = h->restricted_cap;
         return SC_OK;
     }
     return SC_EINVAL;
@@ -338,6 +347,17 @@ int sc_proposer_forward(sc_proposer p, const float *X, int64_t N, int n_cand, in
     return SC_OK;
 }
 
+int sc_screen_topk(sc_dict h, const float *X, int64_t N, int n_cand, int32_t *cand, void *stream) {
+    if (!h || N < 0 || n_cand < 1 || n_cand > 32 || n_cand > h->dev.K) return SC_EINVAL;
+    const int K = h->dev.K;
+    if (K != 128 && K != 256 && K != 512) return SC_EINVAL;
+    if (N == 0) return SC_OK;
+    if (!X || !cand) return SC_EINVAL;
+    hipError_t e = sc::launch_screen_topk(h->Dbf, h->dev.d, K, X, N, n_cand, cand, (hipStream_t)stream);
+    if (e != hipSuccess) return set_dev_error("sc_screen_topk", e);
+    return SC_OK;
+}
+
 size_t sc_omp_encode_learned_workspace(int64_t N, int n_cand) {
     if (N < 0 || n_cand < 1) return 0;
     return align_up(sizeof(int32_t) * (size_t)N * n_cand) + align_up(sizeof(int32_t) * (size_t)N) + kAlign;
@@ -366,7 +386,8 @@ int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, i
     const int refit = (flags & SC_NO_FP64_REFIT) ? 0 : 1;
     SC_HIP(hipMemsetAsync(miss_count, 0, sizeof(int32_t), st), "sc_omp_encode_learned");
     SC_HIP(sc::launch_proposer_topk(p->dev(), X, N, n_cand, cand, nullptr, st), "sc_omp_encode_learned (proposer)");
-    sc::RompParams rp{X, N, k, eps, rel, refit, kKappaMax, cand, n_cand, idx, coef, count, resid, miss_rows,
+    const int kcap = h->restricted_cap > 0 ? std::min(h->restricted_cap, k) : k;
+    sc::RompParams rp{X, N, k, eps, rel, refit, kKappaMax, kcap, cand, n_cand, idx, coef, count, resid, miss_rows,
                       miss_count, h->stats};
     SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, kmax, st), "sc_omp_encode_learned (restricted)");
     sc::OmpParams fp{X, N, miss_rows, miss_count, k, eps, rel, refit, kKappaMax, idx, coef, count, resid, h->stats};
@@ -389,8 +410,9 @@ int sc_omp_encode_restricted(sc_dict h, const float *X, int64_t N, int k, float 
     SC_HIP(hipMemsetAsync(miss_count, 0, sizeof(int32_t), st), "sc_omp_encode_restricted");
     if (N == 0) return SC_OK;
     if (!X || !cand || !idx || !coef || !count || !miss_rows) return SC_EINVAL;
+    const int kcap = h->restricted_cap > 0 ? std::min(h->restricted_cap, k) : k;
     sc::RompParams rp{X, N, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0, (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax,
-                      cand, n_cand, idx, coef, count, resid, miss_rows, miss_count, h->stats};
+                      kcap, cand, n_cand, idx, coef, count, resid, miss_rows, miss_count, h->stats};
     SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, sc::pick_kmax(k), st), "sc_omp_encode_restricted");
     return SC_OK;
 }

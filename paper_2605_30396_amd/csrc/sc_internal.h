@@ -64,6 +64,7 @@ struct RompParams {
     int relative;
     int fp64_refit;
     float kappa_max;
+    int kcap;                 // at most kcap restricted steps (<= k); a signal still above eps is a miss
     const int32_t *cand;      // N x n_cand candidate atoms sorted by index; row {-1,...} = none
     int n_cand;
     int32_t *idx;
@@ -103,6 +104,8 @@ hipError_t launch_omp_restricted(const DictDev &dict, const float *D48, const Ro
                                  hipStream_t st);
 hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16_t *W1b, uint16_t *W2b,
                                 uint16_t *W3b, hipStream_t st);
+hipError_t launch_screen_topk(const uint16_t *Dbf, int d, int K, const float *X, int64_t N, int n_cand,
+                              int32_t *cand, hipStream_t st);
 hipError_t launch_proposer_topk(const PropDev &P, const float *X, int64_t N, int n_cand, int32_t *cand,
                                 float *logits, hipStream_t st);
 enum { EPI_STORE = 0, EPI_GELU = 1, EPI_DGELU = 2 };  // GEMM epilogues (train.hip)
@@ -153,6 +156,7 @@ struct sc_dict_s {
     int a0_fp32 = sc::A0_VALU;       // alpha0 stage of the FP32 encoder (tunable)
     int row_cache = 0;               // Gram rows kept in registers by the encoder (tunable: 0 or 4)
     sc::DictDev *ddev = nullptr;     // device copy of `dev`
+    int restricted_cap = 0;          // restricted-OMP step cap of the learned encoder (0 = k; tunable)
 };
 
 struct sc_proposer_s {

@@ -32,6 +32,7 @@ TRAIN_GRAD_ONLY = 0x2
 
 TUNE_FP32_CORRELATION = 1
 TUNE_ROW_CACHE = 2
+TUNE_RESTRICTED_CAP = 3
 CORR_VALU = 0
 CORR_MFMA = 1
 
@@ -110,6 +111,7 @@ def load():
         "sc_omp_encode_learned_workspace": (C.c_size_t, [I64, I32]),
         "sc_omp_encode_learned": (I32, [P, P, P, I64, I32, F32, I32, I32, P, P, P, P, P, C.c_size_t, P]),
         "sc_omp_encode_restricted": (I32, [P, P, I64, I32, F32, I32, P, I32, P, P, P, P, P, P, P]),
+        "sc_screen_topk": (I32, [P, P, I64, I32, P, P]),
         "sc_omp_encode_rows": (I32, [P, P, P, P, I64, I32, F32, I32, P, P, P, P, P]),
         "sc_omp_encode_batched_workspace": (C.c_size_t, []),
         "sc_omp_encode_batched": (I32, [C.POINTER(Scene), I32, C.POINTER(BatchTuning), P, C.c_size_t, P]),
@@ -330,6 +332,21 @@ def proposer_forward(p: Proposer, X, n_cand=24, want_logits=False, cand=None, st
     _check("sc_proposer_forward", load().sc_proposer_forward(p.handle, _ptr(X), N, int(n_cand), _ptr(cand),
                                                              _ptr(logits), _stream(stream)))
     return cand, logits
+
+
+def screen_topk(h: Dictionary, X, n_cand=24, cand=None, stream=None):
+    """The n_cand atoms of largest |<a_j, x>| per signal (N, n_cand) int32,
+    sorted by atom index (row of -1 = not finite)."""
+    _dev_f32(X, "X", 2)
+    N = X.shape[0]
+    if cand is None:
+        cand = torch.empty((N, n_cand), dtype=torch.int32, device=X.device)
+    else:
+        _dev_i32(cand, "cand", 2)
+        if tuple(cand.shape) != (N, n_cand):
+            raise ValueError(f"cand must have shape {(N, n_cand)}")
+    _check("sc_screen_topk", load().sc_screen_topk(h.handle, _ptr(X), N, int(n_cand), _ptr(cand), _stream(stream)))
+    return cand
 
 
 def learned_workspace_bytes(N, n_cand=24):

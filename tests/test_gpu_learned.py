@@ -165,3 +165,77 @@ def test_learned_edge_signals_and_workspace():
         sc.omp_encode_learned(h, p, Xg, 12, 1e-2, n_cand=8)      # n_cand < k
     h.destroy()
     p.destroy()
+
+
+@pytest.mark.parametrize("K", [128, 256, 512])
+def test_screening_candidates(K):
+    """sc_screen_topk: the n_cand atoms of largest |<a_j, x/||x||>| with D and
+    x/||x|| rounded to BF16 as the kernel does; sets compared where the 24th
+    and 25th values are clearly apart."""
+    rng = I.rng_for(220 + K)
+    D = I.random_dictionary(rng, K)
+    X, _, _ = I.sparse_signals(rng, D, 64 * 7 + 5, 4, 1e-3)
+    X[5] = 0.0
+    X[9, 3] = np.nan
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    cand = sc.screen_topk(h, torch.from_numpy(X).to(DEV), 24).cpu().numpy()
+    h.destroy()
+    Xd = X.astype(np.float64)
+    xn = np.linalg.norm(Xd, axis=1, keepdims=True)
+    xh = oracle.bf16_round(np.where(xn > 0, Xd / np.where(xn > 0, xn, 1), 0.0).astype(np.float32))
+    z = np.abs(xh.astype(np.float64) @ oracle.bf16_round(D).astype(np.float64).T)
+    srt = -np.sort(-z, axis=1)
+    ok = (srt[:, 23] - srt[:, 24]) > 1e-3
+    ok[9] = False
+    assert ok.mean() > 0.2
+    refc = np.sort(oracle.topk_lowest_index(z, 24), axis=1)
+    # K <= 256 cannot overflow the selection slots; at K = 512 a rare overflow
+    # row is -1 (the signal then takes the full-OMP fallback)
+    over = np.all(cand == -1, axis=1)
+    over[9] = False
+    assert over.sum() <= (0 if K <= 256 else 0.01 * len(X)), over.sum()
+    ok &= ~over
+    np.testing.assert_array_equal(cand[ok], refc[ok])
+    assert np.all(cand[9] == -1)
+    valid = np.all(cand >= 0, axis=1)
+    assert np.all(np.diff(cand[valid], axis=1) > 0)
+    assert valid.sum() + over.sum() == len(X) - 1
+
+
+def test_screened_encoder_and_restricted_cap():
+    """Screening -> restricted OMP -> fallback, with and without a cap on the
+    restricted steps: every code either meets eps with at most `cap` atoms
+    from its candidates, or is the full OMP code."""
+    K, k, eps = 512, 12, 1e-2
+    rng = I.rng_for(230)
+    D = I.random_dictionary(rng, K)
+    X, _, _ = I.sparse_signals(rng, D, 3001, 4, 1e-3)
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    Xg = torch.from_numpy(X).to(DEV)
+    cand = sc.screen_topk(h, Xg, 24)
+    full = oracle.omp(D, X, k, eps, with_margin=True, with_path=True)
+    fsep = well_separated(D, X, full, eps)
+    plain = [t.cpu().numpy() for t in sc.omp_encode(h, Xg, k, eps)]
+    for cap in (0, 5):
+        h.set_tuning(sc.TUNE_RESTRICTED_CAP, cap)
+        idx, coef, count, resid, mr, mc = sc.omp_encode_restricted(h, Xg, k, eps, cand)
+        nm = int(mc.item())
+        sc.omp_encode_rows(h, Xg, mr, mc, len(X), k, eps, (idx, coef, count, resid))
+        torch.cuda.synchronize()
+        idx, coef, count, resid = idx.cpu().numpy(), coef.cpu().numpy(), count.cpu().numpy(), resid.cpu().numpy()
+        miss = np.zeros(len(X), bool)
+        miss[mr[:nm].cpu().numpy()] = True
+        acc = ~miss
+        c = cand.cpu().numpy()
+        assert np.all(resid[acc] <= eps * (1 + 1e-6))
+        for i in np.nonzero(acc)[0][::7]:
+            assert set(idx[i, :count[i]]) <= set(c[i])
+        if cap:
+            assert np.all(count[acc] <= cap)
+        # fallback signals carry the plain encoder's code
+        np.testing.assert_array_equal(idx[miss], plain[0][miss])
+        np.testing.assert_array_equal(count[miss], plain[2][miss])
+        chk = miss & fsep
+        np.testing.assert_array_equal(idx[chk], full["idx"][chk])
+        print("cap", cap, "screened misses", nm, "of", len(X))
+    h.destroy()
