@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6_000_000)
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-scene batched comparator")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the tolerance / CSC storage sweep")
     ap.add_argument("--quick", action="store_true",
                     help="headline step only, then a 1 GiB device copy (profiling and counter calibration)")
     args = ap.parse_args()
@@ -316,6 +317,49 @@ def main():
             hq.destroy()
         del scenes, outs
 
+    # ---- tolerance sweep with CSC storage on SH-like coefficients ----
+    sweep = None
+    if not args.no_sweep:
+        from paper_2605_30396_amd import storage
+        t_s = time.perf_counter()
+        w2 = I.workload_sh_like(N=1_000_000)
+        D2 = np.load(os.path.join(ROOT, "tests", "golden", "sh_like_dict_K256.npy"))
+        X2 = torch.from_numpy(w2["X"]).to(dev)
+        N2, K2, k2 = X2.shape[0], D2.shape[0], 32
+        h2 = sc.gram_precompute(torch.from_numpy(D2).to(dev))
+        autotune.tune_dictionary(h2, X2, k2, 0.1, sc.EPS_RELATIVE, use_cache=False)
+        rng2 = np.random.default_rng(57)
+        pos2 = torch.from_numpy(rng2.normal(scale=3.0, size=(N2, 3)).astype(np.float32)).to(dev)
+        dc2 = torch.from_numpy(rng2.normal(scale=1.0, size=(N2, 3)).astype(np.float32)).to(dev)
+        x2n = float(torch.linalg.vector_norm(X2.double()).item())
+        sweep = {"workload": "1e6 SH-like rest vectors (Laplace 0.3*2^-l per band, RGB rho=0.8), K=256 MOD "
+                             "dictionary, relative tolerance, k=32", "points": []}
+
+        def evt(fn):
+            a, b = ev(), ev()
+            fn()
+            torch.cuda.synchronize()
+            a.record(stream)
+            r = fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b), r
+        for tol in (0.03, 0.05, 0.1, 0.2):
+            t_enc, codes = evt(lambda: sc.omp_encode(h2, X2, k2, tol, sc.EPS_RELATIVE))
+            i2, c2, n2, r2 = codes
+            t_pack, packed = evt(lambda: sc.pack_csc(i2, c2, n2))
+            colptr2, rows2, vals2 = packed
+            t_col, _ = evt(lambda: sc.gaussian_rgb_csc(h2, colptr2, rows2, vals2, pos2, dc2, (0.0, 0.0, 10.0)))
+            nnz = int(colptr2[-1].item())
+            sweep["points"].append({
+                "tol": tol, "ms_encode": round(t_enc, 3), "ms_pack_csc": round(t_pack, 3),
+                "ms_colour_step": round(t_col, 4), "mean_atoms": round(nnz / N2, 3),
+                "compression_ratio": round(storage.compression_ratio(N2, nnz, K2), 3),
+                "rel_sh_error": round(float(torch.linalg.vector_norm(r2.double()).item()) / x2n, 5)})
+        log(f"tolerance sweep in {time.perf_counter() - t_s:.1f} s: {sweep['points']}")
+        h2.destroy()
+        del X2, pos2, dc2
+
     # ---- per-kernel rates of the headline step, roofline of the dominant one ----
     phs = results["learned_bf16_proposer"]["phases_ms"]
     ok = np.ones(N, bool)
@@ -381,6 +425,7 @@ def main():
         "comparators": {k2: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k2, v in results.items()},
         "batched": batched,
+        "tolerance_sweep": sweep,
         "kernels": per_kernel,
         "training": {"seconds": round(train_s, 2), "epochs": args.epochs, "train_N": args.train_N,
                      "final_loss": round(hist["loss"][-1], 5), "recall_at_24": recall,

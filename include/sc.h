@@ -340,6 +340,94 @@ int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, i
                            size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Dictionary learning (Sec. 2.1)                                       */
+/* ------------------------------------------------------------------ */
+
+/*
+ * sc_mod_update -- the dictionary half of the alternating minimisation of
+ * Eq. (1) (Sec. 2.1), with the codes fixed: the Method of Optimal Directions
+ *   D = X A^T (A A^T + ridge I)^-1,  ridge = 1e-10 tr(A A^T) / K,
+ * where A (K x N) holds the codes idx/coef/count (as sc_omp_encode writes
+ * them; count < 0 counts as no atom).  Products are accumulated and solved in
+ * FP64.  Atoms no signal uses (or whose solution vanishes) are replaced by
+ * the signals with the largest resid (ties to the lower signal index), then
+ * every atom is scaled to unit norm.  Alternate with sc_gram_precompute +
+ * sc_omp_encode for the full learning loop.
+ *   X          device N x d float32 training signals (N >= 1, d <= 64)
+ *   K          atoms (<= 1024); k: code width (<= 32)
+ *   resid      device float32[N], the codes' residual norms
+ *   D_out      device K x d float32 (out), atom-major, unit-norm atoms
+ *   n_replaced host int (out, may be NULL): atoms replaced
+ *   workspace  device, >= sc_mod_workspace(d, K) bytes
+ * Synchronises `stream` once (to read the number of unused atoms).
+ * Errors: SC_EINVAL, SC_ENOMEM (workspace too small), SC_ENODEV, SC_EDEVICE.
+ */
+size_t sc_mod_workspace(int d, int K);
+int sc_mod_update(const float *X, int64_t N, int d, int K, const int32_t *idx, const float *coef,
+                  const int32_t *count, int k, const float *resid, float *D_out, int *n_replaced, void *workspace,
+                  size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* CSC storage of the codes (Sec. 2.2) and its consumers                */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The paper stores each Gaussian's non-zero coefficients and their atom
+ * indices in Compressed-Sparse-Column form, since the codes differ in length
+ * (Sec. 2.2).  Column i (Gaussian i) is rows/vals[colptr[i] .. colptr[i+1]),
+ * in selection order; a code with count <= 0 (including status -1) is an
+ * empty column.
+ *
+ * sc_csc_colptr -- colptr[i] = sum_{g<i} max(count[g], 0) for i = 0..N
+ * (device int64[N+1]; colptr[N] = number of non-zeros).  workspace: device,
+ * >= sc_csc_workspace(N) bytes.  Read colptr[N] (stream-ordered) to size
+ * rows/vals before sc_csc_fill.
+ * sc_csc_fill -- scatters idx/coef (N x k, padded, as sc_omp_encode writes
+ * them) into rows (int32) / vals (float32) at colptr.
+ * Errors: SC_EINVAL, SC_ENOMEM (workspace too small), SC_EDEVICE.
+ */
+size_t sc_csc_workspace(int64_t N);
+int sc_csc_colptr(const int32_t *count, int64_t N, int64_t *colptr, void *workspace, size_t ws_bytes, void *stream);
+int sc_csc_fill(const int32_t *idx, const float *coef, const int32_t *count, int64_t N, int k, const int64_t *colptr,
+                int32_t *rows, float *vals, void *stream);
+
+/*
+ * sc_omp_encode_csc -- the tolerance-controlled encoder writing CSC (Sec. 2.2
+ * with the eps-controlled sparsity of Sec. 3.2): sc_omp_encode into a
+ * padded workspace, then the column pointers and the variable-length columns
+ * in colptr (device int64[N+1]) / rows / vals.  *nnz_out (host) receives the
+ * number of non-zeros; if it exceeds cap the call returns SC_ENOMEM after
+ * writing colptr, so the caller can size rows/vals (cap = N * k always
+ * suffices) and call again.  resid (device float32[N]) may be NULL.
+ * workspace: device, >= sc_omp_encode_csc_workspace(N, k) bytes.
+ * Synchronises `stream` once (to read the non-zero count).
+ */
+size_t sc_omp_encode_csc_workspace(int64_t N, int k);
+int sc_omp_encode_csc(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, int64_t *colptr,
+                      int32_t *rows, float *vals, int64_t cap, int64_t *nnz_out, float *resid, void *workspace,
+                      size_t ws_bytes, void *stream);
+
+/*
+ * sc_sh_eval_csc -- sc_sh_eval_sparse for codes in CSC form (same sum,
+ * same directions and layouts; an empty column gives rgb = 0).
+ */
+int sc_sh_eval_csc(sc_dict h, const int64_t *colptr, const int32_t *rows, const float *vals, int64_t N,
+                   const float *dirs, int64_t M, int dir_mode, float *rgb, void *stream);
+
+/*
+ * sc_gaussian_rgb_csc -- the renderer's per-Gaussian colour with the
+ * compressed SH (Sec. 2.2, the step Eq. (2)-(3) model): view direction
+ * w = (pos_i - cam) / ||pos_i - cam||, then
+ *   rgb_c = max(0, C0 * dc_ic + sum_t vals_t sum_j D[c*nb + j, rows_t] Y_j(w) + 0.5),
+ * C0 = 1 / (2 sqrt(pi)) (the degree-0 SH constant).
+ *   pos, dc  device N x 3 float32 (Gaussian centres, DC SH coefficients)
+ *   cam      HOST float[3], camera centre
+ *   rgb      device N x 3 float32 (out)
+ */
+int sc_gaussian_rgb_csc(sc_dict h, const int64_t *colptr, const int32_t *rows, const float *vals, int64_t N,
+                        const float *pos, const float *dc, const float cam[3], float *rgb, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Many scenes in one launch                                            */
 /* ------------------------------------------------------------------ */
 

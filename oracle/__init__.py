@@ -9,6 +9,7 @@ Contents:
   mlp_*                      -- the support-proposer network in NumPy FP64
   restricted/learned pursuit -- the proposer-guided encoder, step by step
   mod_learn                  -- dictionary learning by alternating minimisation
+  pack_csc, gaussian_rgb     -- CSC storage of the codes, per-Gaussian colour
 """
 from .core import (  # noqa: F401
     build,
@@ -31,4 +32,5 @@ from .mlp import (  # noqa: F401
     multi_hot,
 )
 from .learned import learned_encode  # noqa: F401
-from .dictlearn import mod_learn  # noqa: F401
+from .dictlearn import mod_learn, mod_step  # noqa: F401
+from .csc import SH_C0, pack_csc, unpack_csc, gaussian_rgb  # noqa: F401

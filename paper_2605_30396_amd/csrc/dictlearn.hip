@@ -1,0 +1,228 @@
+// Dictionary update from fixed sparse codes (Sec. 2.1: Eq. (1) is minimised
+// by alternating between the codes, from the encoder, and the dictionary).
+// The dictionary step is the Method of Optimal Directions:
+//
+//   D = X A^T (A A^T + ridge I)^-1,   ridge = 1e-10 tr(A A^T) / K
+//
+// with A the K x N code matrix.  Both products are accumulated in FP64 from
+// the padded codes (one wave per signal, FP64 atomics into L2), the K x K
+// system is solved by an FP64 Cholesky factorisation in one workgroup, atoms
+// that no signal uses are replaced by the worst-represented signals (largest
+// residual first, ties to the lower signal index), and every atom is scaled
+// to unit norm (the constraint of Eq. (1)).
+#include <algorithm>
+
+#include "sc_internal.h"
+
+namespace sc {
+
+struct ModWork {
+    double *XAt;    // K x d   (row j: sum_i a_ji x_i)
+    double *AAt;    // K x K, then its Cholesky factor (lower)
+    double *Y;      // K x d   solution
+    int *flags;     // K: 1 = atom unused
+    int *nbad;      // count of unused atoms, then the list
+    unsigned long long *key;   // argmax scratch
+};
+
+// One wave per signal: XAt[j_t] += gamma_t x, AAt[j_t][j_u] += gamma_t gamma_u.
+__global__ __launch_bounds__(256) void mod_accum_kernel(const float *__restrict__ X, int64_t N, int d, int K,
+                                                        const int32_t *__restrict__ idx,
+                                                        const float *__restrict__ coef,
+                                                        const int32_t *__restrict__ count, int k, ModWork w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), nw = (int64_t)gridDim.x * 4;
+    for (int64_t i = gw; i < N; i += nw) {
+        int n = count[i];
+        n = n < 0 ? 0 : (n > k ? k : n);
+        if (n == 0) continue;
+        const double xv = lane < d ? (double)X[i * d + lane] : 0.0;
+        const int jl = lane < n ? idx[i * k + lane] : 0;
+        const double gl = lane < n ? (double)coef[i * k + lane] : 0.0;
+        for (int t = 0; t < n; ++t) {
+            const int jt = __shfl(jl, t, 64);
+            const double gt = __shfl(gl, t, 64);
+            if (jt < 0 || jt >= K) continue;
+            if (lane < d) atomicAdd(&w.XAt[(size_t)jt * d + lane], gt * xv);
+            if (lane < n) {
+                if (jl >= 0 && jl < K) atomicAdd(&w.AAt[(size_t)jt * K + jl], gt * gl);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double *red) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int q = 0; q < nw; ++q) s += red[q];
+    return s;
+}
+
+// One workgroup: ridge, Cholesky of A A^T + ridge I, two triangular solves
+// for the d right-hand sides, unused-atom flags.
+__global__ __launch_bounds__(1024) void mod_solve_kernel(int d, int K, ModWork w) {
+    __shared__ double red[16];
+    __shared__ double diag_sh;
+    double *A = w.AAt;
+    // unused atoms and the trace
+    double tr = 0.0;
+    for (int j = threadIdx.x; j < K; j += blockDim.x) {
+        const double a = A[(size_t)j * K + j];
+        tr += a;
+        w.flags[j] = a > 0.0 ? 0 : 1;
+    }
+    tr = block_sum_d(tr, red);
+    const double ridge = 1e-10 * tr / K;
+    for (int j = threadIdx.x; j < K; j += blockDim.x) A[(size_t)j * K + j] += ridge;
+    __syncthreads();
+    // left-looking Cholesky, column by column: A = L L^T in the lower triangle
+    for (int j = 0; j < K; ++j) {
+        double s = 0.0;
+        for (int p = threadIdx.x; p < j; p += blockDim.x) {
+            const double l = A[(size_t)j * K + p];
+            s += l * l;
+        }
+        s = block_sum_d(s, red);
+        if (threadIdx.x == 0) {
+            const double v = A[(size_t)j * K + j] - s;
+            diag_sh = sqrt(v > 1e-300 ? v : 1e-300);
+            A[(size_t)j * K + j] = diag_sh;
+        }
+        __syncthreads();
+        const double ljj = diag_sh;
+        for (int i = j + 1 + threadIdx.x; i < K; i += blockDim.x) {
+            double v = A[(size_t)i * K + j];
+            for (int p = 0; p < j; ++p) v -= A[(size_t)i * K + p] * A[(size_t)j * K + p];
+            A[(size_t)i * K + j] = v / ljj;
+        }
+        __syncthreads();
+    }
+    // L Z = XAt, then L^T Y = Z, one right-hand side (feature) per thread
+    for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        for (int i = 0; i < K; ++i) {
+            double v = w.XAt[(size_t)i * d + c];
+            for (int p = 0; p < i; ++p) v -= A[(size_t)i * K + p] * w.Y[(size_t)p * d + c];
+            w.Y[(size_t)i * d + c] = v / A[(size_t)i * K + i];
+        }
+        for (int i = K - 1; i >= 0; --i) {
+            double v = w.Y[(size_t)i * d + c];
+            for (int p = i + 1; p < K; ++p) v -= A[(size_t)p * K + i] * w.Y[(size_t)p * d + c];
+            w.Y[(size_t)i * d + c] = v / A[(size_t)i * K + i];
+        }
+    }
+    __syncthreads();
+    // atoms with a vanishing solution count as unused too
+    for (int j = threadIdx.x; j < K; j += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < d; ++c) s += w.Y[(size_t)j * d + c] * w.Y[(size_t)j * d + c];
+        if (!(sqrt(s) > 1e-12)) w.flags[j] = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nb = 0;
+        for (int j = 0; j < K; ++j)
+            if (w.flags[j]) w.nbad[1 + nb++] = j;
+        w.nbad[0] = nb;
+    }
+}
+
+// Largest residual with key below *prev (keys: residual order bits high,
+// ~index low, so equal residuals resolve to the lower index).
+__global__ __launch_bounds__(256) void mod_worst_kernel(const float *__restrict__ resid, int64_t N,
+                                                        unsigned long long prev, unsigned long long *key) {
+    unsigned long long best = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const float r = resid[i];
+        const uint32_t u = __float_as_uint(isfinite(r) ? r : 0.f);
+        const uint32_t ok = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+        const unsigned long long kk = ((unsigned long long)ok << 32) | (0xFFFFFFFFull - (unsigned long long)i);
+        if (kk < prev && kk > best) best = kk;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off, 64);
+        best = o > best ? o : best;
+    }
+    if ((threadIdx.x & 63) == 0 && best) atomicMax(key, best);
+}
+
+__global__ void mod_zero_key_kernel(unsigned long long *key) {
+    if (threadIdx.x == 0) *key = 0;
+}
+
+// Row `slot` of the unused-atom list takes signal X[index of *key].
+__global__ void mod_replace_kernel(const float *__restrict__ X, int d, int slot, ModWork w) {
+    const int j = w.nbad[1 + slot];
+    const int64_t i = (int64_t)(0xFFFFFFFFull - (*w.key & 0xFFFFFFFFull));
+    for (int c = threadIdx.x; c < d; c += blockDim.x) w.Y[(size_t)j * d + c] = (double)X[i * d + c];
+}
+
+__global__ void mod_normalise_kernel(int d, int K, ModWork w, float *__restrict__ Dout) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K) return;
+    double s = 0.0;
+    for (int c = 0; c < d; ++c) s += w.Y[(size_t)j * d + c] * w.Y[(size_t)j * d + c];
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int c = 0; c < d; ++c) Dout[(size_t)j * d + c] = (float)(w.Y[(size_t)j * d + c] * inv);
+}
+
+static size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t mod_workspace_bytes(int d, int K) {
+    return al256(sizeof(double) * (size_t)K * d) * 2 + al256(sizeof(double) * (size_t)K * K) +
+           al256(sizeof(int) * (size_t)K) + al256(sizeof(int) * (size_t)(K + 1)) + al256(sizeof(unsigned long long));
+}
+
+static ModWork mod_layout(void *ws, int d, int K) {
+    unsigned char *p = (unsigned char *)ws;
+    ModWork w;
+    w.XAt = (double *)p;
+    p += al256(sizeof(double) * (size_t)K * d);
+    w.AAt = (double *)p;
+    p += al256(sizeof(double) * (size_t)K * K);
+    w.Y = (double *)p;
+    p += al256(sizeof(double) * (size_t)K * d);
+    w.flags = (int *)p;
+    p += al256(sizeof(int) * (size_t)K);
+    w.nbad = (int *)p;
+    p += al256(sizeof(int) * (size_t)(K + 1));
+    w.key = (unsigned long long *)p;
+    return w;
+}
+
+// Stream-ordered except for one read of the unused-atom count.
+hipError_t launch_mod_update(const float *X, int64_t N, int d, int K, const int32_t *idx, const float *coef,
+                             const int32_t *count, int k, const float *resid, float *Dout, int *n_replaced, void *ws,
+                             hipStream_t st) {
+    ModWork w = mod_layout(ws, d, K);
+    hipError_t e;
+    if ((e = hipMemsetAsync(w.XAt, 0, sizeof(double) * (size_t)K * d, st)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(w.AAt, 0, sizeof(double) * (size_t)K * K, st)) != hipSuccess) return e;
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((N + 3) / 4, (int64_t)ncu * 8));
+    hipLaunchKernelGGL(mod_accum_kernel, dim3((unsigned)grid), dim3(256), 0, st, X, N, d, K, idx, coef, count, k, w);
+    hipLaunchKernelGGL(mod_solve_kernel, dim3(1), dim3(1024), 0, st, d, K, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int nb = 0;
+    if ((e = hipMemcpyAsync(&nb, w.nbad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    unsigned long long prev = ~0ull;
+    for (int s = 0; s < nb; ++s) {
+        hipLaunchKernelGGL(mod_zero_key_kernel, dim3(1), dim3(64), 0, st, w.key);
+        const int64_t g2 = std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, (int64_t)ncu * 4));
+        hipLaunchKernelGGL(mod_worst_kernel, dim3((unsigned)g2), dim3(256), 0, st, resid, N, prev, w.key);
+        hipLaunchKernelGGL(mod_replace_kernel, dim3(1), dim3(64), 0, st, X, d, s, w);
+        if ((e = hipMemcpyAsync(&prev, w.key, sizeof(prev), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(mod_normalise_kernel, dim3((K + 255) / 256), dim3(256), 0, st, d, K, w, Dout);
+    if (n_replaced) *n_replaced = nb;
+    return hipGetLastError();
+}
+
+}  // namespace sc

@@ -12,15 +12,15 @@
 // selection needs no transpose:
 //   1. each lane takes maxima of groups of K/32 of its logits: 32 group
 //      maxima per signal;
-//   2. theta = the n_cand-th largest group maximum is a safe lower bound of
-//      the n_cand-th largest logit (n_cand groups reach it);
+//   2. theta = the n_cand-th largest group maximum (sorted by one thread per
+//      signal) is a safe lower bound of the n_cand-th largest logit, since
+//      n_cand groups reach it;
 //   3. each writer lane appends its logits >= theta to a private slot list,
 //      as keys that order like the logit with the atom index in the low bits
-//      (unique keys, lower index wins a tie);
-//   4. eight lanes per signal (eight signals per wave at once) find the
-//      n_cand-th largest key by a bitwise search with group-summed counts,
-//      mark the chosen atoms in a bit mask and write them in increasing atom
-//      index.
+//      (unique keys, lower index wins a tie) -- about n_cand + 17 survivors;
+//   4. eight lanes per signal (eight signals per wave at once) delete the
+//      smallest survivor until n_cand remain, mark the chosen atoms in a bit
+//      mask and write them in increasing atom index.
 // A signal whose slot lists overflow (many logits tied at the threshold) or
 // whose input is not finite gets candidate list {-1, ...}: the encoder then
 // sends it straight to the full-OMP fallback.  Keys keep the top 32 - IB bits
@@ -68,6 +68,20 @@ __device__ __forceinline__ int grp8_sum(int v) {
     v += __builtin_amdgcn_update_dpp(0, v, SC_DPP_QP1032, 0xF, 0xF, false);
     v += __builtin_amdgcn_update_dpp(0, v, SC_DPP_QP2301, 0xF, 0xF, false);
     v += __builtin_amdgcn_update_dpp(0, v, SC_DPP_HMIRROR, 0xF, 0xF, false);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t grp8_min(uint32_t v) {
+    v = min(v, dpp_u<SC_DPP_QP1032>(v));
+    v = min(v, dpp_u<SC_DPP_QP2301>(v));
+    v = min(v, dpp_u<SC_DPP_HMIRROR>(v));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t grp8_max(uint32_t v) {
+    v = max(v, dpp_u<SC_DPP_QP1032>(v));
+    v = max(v, dpp_u<SC_DPP_QP2301>(v));
+    v = max(v, dpp_u<SC_DPP_HMIRROR>(v));
     return v;
 }
 
@@ -136,8 +150,8 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     int *bad = reinterpret_cast<int *>(lds + kXBytes + 2 * kHBytes);
     // reused once layer 3 is done (Xh, H1 and H2 are dead then); the group
     // maxima are dead once theta is known, so the slots overlay them
-    float *theta = reinterpret_cast<float *>(lds);                              // [64]
-    uint32_t *mask = reinterpret_cast<uint32_t *>(theta + kPT);                // [64][MW]
+    uint32_t *theta = reinterpret_cast<uint32_t *>(lds);                       // [64] threshold keys
+    uint32_t *mask = theta + kPT;                                               // [64][MW]
     uint8_t *wcnt = reinterpret_cast<uint8_t *>(mask + kPT * MW);              // [64][NWR]
     float *gmax = reinterpret_cast<float *>(wcnt + kPT * NWR);                 // [64][32]
     uint32_t *slots = reinterpret_cast<uint32_t *>(gmax);                      // [64][NWR][kSlots]
@@ -270,34 +284,34 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             }
         }
         __syncthreads();
-        // ---- safe threshold per signal ----
+        // ---- threshold: the n_cand-th largest group maximum (one thread per signal) ----
         if (tid < kPT) {
-            float v[32];
+            float v[kNG];
 #pragma unroll
-            for (int g = 0; g < 32; ++g) v[g] = gmax[tid * kNG + g];
+            for (int g = 0; g < kNG; ++g) v[g] = gmax[tid * kNG + g];
             sort32_desc(v);
             float th = v[0];
 #pragma unroll
-            for (int g = 0; g < 32; ++g)
+            for (int g = 0; g < kNG; ++g)
                 if (g == n_cand - 1) th = v[g];
-            theta[tid] = bad[tid] ? __builtin_inff() : th;
+            theta[tid] = bad[tid] ? 0xFFFFFFFFu : order_key(th);
         }
         __syncthreads();
         // ---- candidates above the threshold, into private slots ----
 #pragma unroll
         for (int n = 0; n < NPW; ++n) {
             const int j = 32 * (n0 + n) + lr;
-            const float th = theta[j];
+            const uint32_t thk = theta[j];
             uint32_t *myslots = slots + (j * NWR + wr) * kSlots;
             int cnt = 0;
 #pragma unroll
             for (int q = 0; q < MPW; ++q)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const float z = acc[q][n][r];
-                    if (z >= th) {
+                    const uint32_t zk = order_key(acc[q][n][r]);
+                    if (zk >= thk) {
                         const int i = 32 * mblk(q) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                        if (cnt < kSlots) myslots[cnt] = (order_key(z) & ~IMASK) | (IMASK - (uint32_t)i);
+                        if (cnt < kSlots) myslots[cnt] = (zk & ~IMASK) | (IMASK - (uint32_t)i);
                         ++cnt;
                     }
                 }
@@ -324,19 +338,25 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             over = grp8_sum(over);
             have = grp8_sum(have);
             const bool skip = s >= nt_sig || bad[s] || over || have < n_cand;
-            // largest tau with #{key >= tau} >= n_cand: the n_cand-th largest key
-            // (empty slots hold 0, which no t2 >= 1 counts)
-            uint32_t tau = 0;
-            for (int bit = 31; bit >= 0; --bit) {
-                const uint32_t t2 = tau | (1u << bit);
-                int c = 0;
+            // delete the smallest survivor until n_cand remain (keys are
+            // unique; an empty slot holds 0, i.e. ~0 after the shift below)
+            int excess = skip ? 0 : have - n_cand;
+            while (__ballot(excess > 0) != 0) {
+                uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
                 for (int w = 0; w < WPL; ++w)
 #pragma unroll
                     for (int e = 0; e < kSlots; ++e)
-                        if ((uint32_t)e < lim[w]) c += key[w * kSlots + e] >= t2 ? 1 : 0;
-                c = grp8_sum(c);
-                tau = c >= n_cand ? t2 : tau;
+                        if ((uint32_t)e < lim[w]) mn = min(mn, key[w * kSlots + e] - 1u);
+                mn = grp8_min(mn);
+                if (excess > 0) {
+#pragma unroll
+                    for (int w = 0; w < WPL; ++w)
+#pragma unroll
+                        for (int e = 0; e < kSlots; ++e)
+                            if ((uint32_t)e < lim[w] && key[w * kSlots + e] - 1u == mn) key[w * kSlots + e] = 0u;
+                    --excess;
+                }
             }
             // mark the chosen atoms, then list them in increasing index
             uint32_t *mw = mask + s * MW;
@@ -347,7 +367,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             if (!skip) {
 #pragma unroll
                 for (int e = 0; e < WPL * kSlots; ++e)
-                    if (key[e] >= tau && key[e] != 0u) {
+                    if (key[e] != 0u) {
                         const uint32_t i = IMASK - (key[e] & IMASK);
                         atomicOr(&mw[i >> 5], 1u << (i & 31));
                     }

@@ -253,6 +253,126 @@ int sc_sh_eval_sparse(sc_dict h, const int32_t *idx, const float *coef, const in
 }
 
 /* ------------------------------------------------------------------ */
+/* dictionary update                                                    */
+/* ------------------------------------------------------------------ */
+
+size_t sc_mod_workspace(int d, int K) {
+    if (d < 1 || d > 64 || K < 1 || K > 1024) return 0;
+    return sc::mod_workspace_bytes(d, K);
+}
+
+int sc_mod_update(const float *X, int64_t N, int d, int K, const int32_t *idx, const float *coef,
+                  const int32_t *count, int k, const float *resid, float *D_out, int *n_replaced, void *workspace,
+                  size_t ws_bytes, void *stream) {
+    if (N < 1 || d < 1 || d > 64 || K < 1 || K > 1024 || k < 1 || k > 32) return SC_EINVAL;
+    if (!X || !idx || !coef || !count || !resid || !D_out || !workspace) return SC_EINVAL;
+    if (ws_bytes < sc_mod_workspace(d, K)) return SC_ENOMEM;
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc != SC_OK) return rc;
+    SC_HIP(sc::launch_mod_update(X, N, d, K, idx, coef, count, k, resid, D_out, n_replaced, workspace,
+                                 (hipStream_t)stream),
+           "sc_mod_update");
+    return SC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* CSC storage and its consumers                                        */
+/* ------------------------------------------------------------------ */
+
+size_t sc_csc_workspace(int64_t N) {
+    if (N < 0) return 0;
+    return align_up(sizeof(int64_t) * (size_t)(sc::csc_workspace_blocks(N) + 1));
+}
+
+int sc_csc_colptr(const int32_t *count, int64_t N, int64_t *colptr, void *workspace, size_t ws_bytes, void *stream) {
+    if (N < 0 || !colptr) return SC_EINVAL;
+    if (N > 0 && !count) return SC_EINVAL;
+    if (!workspace) return SC_EINVAL;
+    if (ws_bytes < sc_csc_workspace(N)) return SC_ENOMEM;
+    SC_HIP(sc::launch_csc_colptr(count, N, colptr, (int64_t *)workspace, (hipStream_t)stream), "sc_csc_colptr");
+    return SC_OK;
+}
+
+int sc_csc_fill(const int32_t *idx, const float *coef, const int32_t *count, int64_t N, int k, const int64_t *colptr,
+                int32_t *rows, float *vals, void *stream) {
+    if (N < 0 || k < 1 || k > 1024) return SC_EINVAL;
+    if (N == 0) return SC_OK;
+    if (!idx || !coef || !count || !colptr || !rows || !vals) return SC_EINVAL;
+    SC_HIP(sc::launch_csc_fill(idx, coef, count, N, k, colptr, rows, vals, (hipStream_t)stream), "sc_csc_fill");
+    return SC_OK;
+}
+
+size_t sc_omp_encode_csc_workspace(int64_t N, int k) {
+    if (N < 0 || k < 1 || k > 32) return 0;
+    return align_up(sizeof(int32_t) * (size_t)N * k) * 2 + align_up(sizeof(int32_t) * (size_t)N) +
+           align_up(sizeof(float) * (size_t)N) + sc_csc_workspace(N) + kAlign;
+}
+
+int sc_omp_encode_csc(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, int64_t *colptr,
+                      int32_t *rows, float *vals, int64_t cap, int64_t *nnz_out, float *resid, void *workspace,
+                      size_t ws_bytes, void *stream) {
+    if (!h || N < 0 || cap < 0 || !colptr || !nnz_out) return SC_EINVAL;
+    if (k < 1 || k > std::min(std::min(h->dev.K, h->dev.d), 32)) return SC_EINVAL;
+    if (!workspace) return SC_EINVAL;
+    if (ws_bytes < sc_omp_encode_csc_workspace(N, k)) return SC_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *w = (unsigned char *)workspace;
+    int32_t *idx = (int32_t *)w;
+    w += align_up(sizeof(int32_t) * (size_t)N * k);
+    float *coef = (float *)w;
+    w += align_up(sizeof(int32_t) * (size_t)N * k);
+    int32_t *count = (int32_t *)w;
+    w += align_up(sizeof(int32_t) * (size_t)N);
+    float *res = resid ? resid : (float *)w;
+    w += align_up(sizeof(float) * (size_t)N);
+    int rc = sc_omp_encode(h, X, N, k, eps, flags, idx, coef, count, res, stream);
+    if (rc != SC_OK) return rc;
+    rc = sc_csc_colptr(count, N, colptr, w, sc_csc_workspace(N), stream);
+    if (rc != SC_OK) return rc;
+    int64_t nnz = 0;
+    SC_HIP(hipMemcpyAsync(&nnz, colptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, st), "sc_omp_encode_csc");
+    SC_HIP(hipStreamSynchronize(st), "sc_omp_encode_csc");
+    *nnz_out = nnz;
+    if (nnz > cap) return SC_ENOMEM;
+    if (nnz > 0 && (!rows || !vals)) return SC_EINVAL;
+    return N > 0 ? sc_csc_fill(idx, coef, count, N, k, colptr, rows, vals, stream) : SC_OK;
+}
+
+int sc_sh_eval_csc(sc_dict h, const int64_t *colptr, const int32_t *rows, const float *vals, int64_t N,
+                   const float *dirs, int64_t M, int dir_mode, float *rgb, void *stream) {
+    if (!h || N < 0) return SC_EINVAL;
+    const int d = h->dev.d;
+    if (d != 9 && d != 24 && d != 45) return SC_EINVAL;
+    if (dir_mode == SC_DIRS_PER_SIGNAL) {
+        if (M != N) return SC_EINVAL;
+    } else if (dir_mode == SC_DIRS_SHARED) {
+        if (M < 1) return SC_EINVAL;
+    } else {
+        return SC_EINVAL;
+    }
+    if (N == 0) return SC_OK;
+    if (!colptr || !rows || !vals || !dirs || !rgb) return SC_EINVAL;
+    SC_HIP(sc::launch_csc_eval(h->dev, colptr, rows, vals, N, dirs, M, dir_mode == SC_DIRS_SHARED ? 1 : 0, nullptr,
+                               nullptr, nullptr, rgb, (hipStream_t)stream),
+           "sc_sh_eval_csc");
+    return SC_OK;
+}
+
+int sc_gaussian_rgb_csc(sc_dict h, const int64_t *colptr, const int32_t *rows, const float *vals, int64_t N,
+                        const float *pos, const float *dc, const float cam[3], float *rgb, void *stream) {
+    if (!h || N < 0 || !cam) return SC_EINVAL;
+    const int d = h->dev.d;
+    if (d != 9 && d != 24 && d != 45) return SC_EINVAL;
+    if (!isfinite(cam[0]) || !isfinite(cam[1]) || !isfinite(cam[2])) return SC_EINVAL;
+    if (N == 0) return SC_OK;
+    if (!colptr || !rows || !vals || !pos || !dc || !rgb) return SC_EINVAL;
+    SC_HIP(sc::launch_csc_eval(h->dev, colptr, rows, vals, N, nullptr, N, 0, pos, dc, cam, rgb, (hipStream_t)stream),
+           "sc_gaussian_rgb_csc");
+    return SC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* learned support proposer                                             */
 /* ------------------------------------------------------------------ */
 

@@ -136,6 +136,17 @@ hipError_t launch_bce_grad(const float *Z, int64_t B, int K, const int32_t *rows
 hipError_t launch_colsum(const void *A, int64_t M, int N, int64_t ld, float *out, bool f32, hipStream_t st);
 hipError_t launch_adam(float *p, float *m, float *v, const float *g, int64_t n, float lr_t, float beta1, float beta2,
                        float eps_hat, hipStream_t st);
+size_t mod_workspace_bytes(int d, int K);
+hipError_t launch_mod_update(const float *X, int64_t N, int d, int K, const int32_t *idx, const float *coef,
+                             const int32_t *count, int k, const float *resid, float *Dout, int *n_replaced, void *ws,
+                             hipStream_t st);
+int64_t csc_workspace_blocks(int64_t N);
+hipError_t launch_csc_colptr(const int32_t *count, int64_t N, int64_t *colptr, int64_t *bsum, hipStream_t st);
+hipError_t launch_csc_fill(const int32_t *idx, const float *coef, const int32_t *count, int64_t N, int k,
+                           const int64_t *colptr, int32_t *rows, float *vals, hipStream_t st);
+hipError_t launch_csc_eval(const DictDev &dict, const int64_t *colptr, const int32_t *rows, const float *vals,
+                           int64_t N, const float *dirs, int64_t M, int shared, const float *pos, const float *dc,
+                           const float *cam, float *rgb, hipStream_t st);
 hipError_t launch_sh_eval(const DictDev &dict, const int32_t *idx, const float *coef, const int32_t *count,
                           int64_t N, int k, const float *dirs, int64_t M, int shared, float *rgb,
                           hipStream_t st);

@@ -113,6 +113,15 @@ def load():
         "sc_omp_encode_restricted": (I32, [P, P, I64, I32, F32, I32, P, I32, P, P, P, P, P, P, P]),
         "sc_screen_topk": (I32, [P, P, I64, I32, P, P]),
         "sc_omp_encode_rows": (I32, [P, P, P, P, I64, I32, F32, I32, P, P, P, P, P]),
+        "sc_mod_workspace": (C.c_size_t, [I32, I32]),
+        "sc_mod_update": (I32, [P, I64, I32, I32, P, P, P, I32, P, P, C.POINTER(I32), P, C.c_size_t, P]),
+        "sc_csc_workspace": (C.c_size_t, [I64]),
+        "sc_omp_encode_csc_workspace": (C.c_size_t, [I64, I32]),
+        "sc_omp_encode_csc": (I32, [P, P, I64, I32, F32, I32, P, P, P, I64, C.POINTER(I64), P, P, C.c_size_t, P]),
+        "sc_csc_colptr": (I32, [P, I64, P, P, C.c_size_t, P]),
+        "sc_csc_fill": (I32, [P, P, P, I64, I32, P, P, P, P]),
+        "sc_sh_eval_csc": (I32, [P, P, P, P, I64, P, I64, I32, P, P]),
+        "sc_gaussian_rgb_csc": (I32, [P, P, P, P, I64, P, P, C.POINTER(F32), P, P]),
         "sc_omp_encode_batched_workspace": (C.c_size_t, []),
         "sc_omp_encode_batched": (I32, [C.POINTER(Scene), I32, C.POINTER(BatchTuning), P, C.c_size_t, P]),
         "sc_batch_autotune": (I32, [C.POINTER(Scene), I32, I64, P, C.c_size_t, C.POINTER(BatchTuning),
@@ -490,3 +499,95 @@ def batch_autotune(scenes, sample=65536, workspace=None, stream=None):
                                                          workspace.numel(), C.byref(best), C.byref(ms),
                                                          _stream(stream)))
     return best, float(ms.value)
+
+
+# ----------------------------------------------------------------------------
+# CSC storage of the codes
+# ----------------------------------------------------------------------------
+
+def pack_csc(idx, coef, count, stream=None):
+    """Codes (N x k padded) -> (colptr int64[N+1], rows int32[nnz], vals
+    float32[nnz]) on the device.  Synchronises once to read nnz."""
+    _dev_i32(idx, "idx", 2)
+    _dev_f32(coef, "coef", 2)
+    _dev_i32(count, "count", 1)
+    N, k = idx.shape
+    lib = load()
+    colptr = torch.empty((N + 1,), dtype=torch.int64, device=idx.device)
+    ws = torch.empty(max(int(lib.sc_csc_workspace(N)), 1), dtype=torch.uint8, device=idx.device)
+    _check("sc_csc_colptr", lib.sc_csc_colptr(_ptr(count), N, _ptr(colptr), _ptr(ws), ws.numel(), _stream(stream)))
+    nnz = int(colptr[N].item())
+    rows = torch.empty((max(nnz, 1),), dtype=torch.int32, device=idx.device)
+    vals = torch.empty((max(nnz, 1),), dtype=torch.float32, device=idx.device)
+    _check("sc_csc_fill", lib.sc_csc_fill(_ptr(idx), _ptr(coef), _ptr(count), N, k, _ptr(colptr), _ptr(rows),
+                                          _ptr(vals), _stream(stream)))
+    return colptr, rows[:nnz], vals[:nnz]
+
+
+def omp_encode_csc(h: Dictionary, X, k, eps=0.0, flags=0, cap=None, stream=None):
+    """Encode straight to CSC: returns (colptr int64[N+1], rows int32[nnz],
+    vals float32[nnz], resid float32[N])."""
+    _dev_f32(X, "X", 2)
+    N = X.shape[0]
+    lib = load()
+    ws = torch.empty(max(int(lib.sc_omp_encode_csc_workspace(N, k)), 1), dtype=torch.uint8, device=X.device)
+    colptr = torch.empty((N + 1,), dtype=torch.int64, device=X.device)
+    resid = torch.empty((max(N, 1),), dtype=torch.float32, device=X.device)
+    cap = N * k if cap is None else int(cap)
+    rows = torch.empty((max(cap, 1),), dtype=torch.int32, device=X.device)
+    vals = torch.empty((max(cap, 1),), dtype=torch.float32, device=X.device)
+    nnz = C.c_int64(0)
+    _check("sc_omp_encode_csc", lib.sc_omp_encode_csc(h.handle, _ptr(X), N, int(k), float(eps), int(flags),
+                                                      _ptr(colptr), _ptr(rows), _ptr(vals), cap, C.byref(nnz),
+                                                      _ptr(resid), _ptr(ws), ws.numel(), _stream(stream)))
+    n = int(nnz.value)
+    return colptr, rows[:n], vals[:n], resid[:N]
+
+
+def sh_eval_csc(h: Dictionary, colptr, rows, vals, dirs, dir_mode=DIRS_PER_SIGNAL, out=None, stream=None):
+    N = colptr.shape[0] - 1
+    M = dirs.shape[0]
+    if out is None:
+        shape = (N, 3) if dir_mode == DIRS_PER_SIGNAL else (N, M, 3)
+        out = torch.empty(shape, dtype=torch.float32, device=dirs.device)
+    _check("sc_sh_eval_csc", load().sc_sh_eval_csc(h.handle, _ptr(colptr), _ptr(rows), _ptr(vals), N, _ptr(dirs), M,
+                                                   int(dir_mode), _ptr(out), _stream(stream)))
+    return out
+
+
+def gaussian_rgb_csc(h: Dictionary, colptr, rows, vals, pos, dc, cam, out=None, stream=None):
+    """Per-Gaussian colour max(0, C0 dc + SH_rest(view dir) + 0.5) from CSC codes."""
+    N = colptr.shape[0] - 1
+    _dev_f32(pos, "pos", 2)
+    _dev_f32(dc, "dc", 2)
+    if out is None:
+        out = torch.empty((N, 3), dtype=torch.float32, device=pos.device)
+    c = (C.c_float * 3)(*[float(v) for v in cam])
+    _check("sc_gaussian_rgb_csc", load().sc_gaussian_rgb_csc(h.handle, _ptr(colptr), _ptr(rows), _ptr(vals), N,
+                                                             _ptr(pos), _ptr(dc), c, _ptr(out), _stream(stream)))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# dictionary learning
+# ----------------------------------------------------------------------------
+
+def mod_update(X, idx, coef, count, resid, K, out=None, workspace=None, stream=None):
+    """One dictionary update from fixed codes; returns ((K, d) float32 CUDA
+    tensor of unit atoms, number of atoms replaced)."""
+    _dev_f32(X, "X", 2)
+    _dev_i32(idx, "idx", 2)
+    _dev_f32(coef, "coef", 2)
+    _dev_i32(count, "count", 1)
+    _dev_f32(resid, "resid", 1)
+    N, d = X.shape
+    lib = load()
+    if out is None:
+        out = torch.empty((K, d), dtype=torch.float32, device=X.device)
+    if workspace is None:
+        workspace = torch.empty(max(int(lib.sc_mod_workspace(d, K)), 1), dtype=torch.uint8, device=X.device)
+    nrep = C.c_int32(0)
+    _check("sc_mod_update", lib.sc_mod_update(_ptr(X), N, d, int(K), _ptr(idx), _ptr(coef), _ptr(count),
+                                              idx.shape[1], _ptr(resid), _ptr(out), C.byref(nrep), _ptr(workspace),
+                                              workspace.numel(), _stream(stream)))
+    return out, int(nrep.value)
