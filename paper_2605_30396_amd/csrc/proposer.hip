@@ -10,14 +10,14 @@
 // per tile, and the A operands are prefetched several k-steps ahead.  In the
 // MFMA output layout a lane holds 16 outputs of one signal per block, so the
 // selection needs no transpose:
-//   1. each lane takes maxima of groups of K/32 of its logits: 32 group
+//   1. each lane takes maxima of groups of K/64 of its logits: 64 group
 //      maxima per signal;
-//   2. theta = the n_cand-th largest group maximum (sorted by one thread per
-//      signal) is a safe lower bound of the n_cand-th largest logit, since
-//      n_cand groups reach it;
+//   2. theta = the n_cand-th largest group maximum (eight lanes per signal,
+//      bitwise search with group-summed counts) is a safe lower bound of the
+//      n_cand-th largest logit, since n_cand groups reach it;
 //   3. each writer lane appends its logits >= theta to a private slot list,
 //      as keys that order like the logit with the atom index in the low bits
-//      (unique keys, lower index wins a tie) -- about n_cand + 17 survivors;
+//      (unique keys, lower index wins a tie) -- about n_cand + 5 survivors;
 //   4. eight lanes per signal (eight signals per wave at once) delete the
 //      smallest survivor until n_cand remain, mark the chosen atoms in a bit
 //      mask and write them in increasing atom index.
@@ -38,30 +38,11 @@ constexpr int kPThreads = 64 * kPWaves;
 constexpr int kPH = 256;       // hidden width
 constexpr int kXS = 72;        // LDS row stride (bf16) of the input tile
 constexpr int kHS = 264;       // LDS row stride (bf16) of a hidden tile
-constexpr int kNG = 32;        // group maxima per signal
+constexpr int kNG = 64;        // group maxima per signal
 
 constexpr int kXBytes = kPT * kXS * 2;        //  9216
 constexpr int kHBytes = kPT * kHS * 2;        // 33792
 constexpr int kPropLds = kXBytes + 2 * kHBytes + kPT * 4;
-
-// Sort n = 32 floats descending in registers (bitonic network).
-__device__ __forceinline__ void sort32_desc(float *v) {
-#pragma unroll
-    for (int k = 2; k <= 32; k <<= 1)
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1)
-#pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                int p = i ^ j;
-                if (p > i) {
-                    bool desc = (i & k) == 0;
-                    float a = v[i], b = v[p];
-                    float hi = fmaxf(a, b), lo = fminf(a, b);
-                    v[i] = desc ? hi : lo;
-                    v[p] = desc ? lo : hi;
-                }
-            }
-}
 
 // Sum over the 8 lanes of a group (lanes 8q .. 8q+7).
 __device__ __forceinline__ int grp8_sum(int v) {
@@ -284,17 +265,35 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             }
         }
         __syncthreads();
-        // ---- threshold: the n_cand-th largest group maximum (one thread per signal) ----
-        if (tid < kPT) {
-            float v[kNG];
+        // ---- threshold: the n_cand-th largest of the 64 group maxima ----
+        {
+            const int g = lane & 7, s = 8 * wave + (lane >> 3);
+            uint32_t gk[8];
+            const float4 ga = *reinterpret_cast<const float4 *>(gmax + s * kNG + 8 * g);
+            const float4 gb = *reinterpret_cast<const float4 *>(gmax + s * kNG + 8 * g + 4);
+            gk[0] = order_key(ga.x), gk[1] = order_key(ga.y), gk[2] = order_key(ga.z), gk[3] = order_key(ga.w);
+            gk[4] = order_key(gb.x), gk[5] = order_key(gb.y), gk[6] = order_key(gb.z), gk[7] = order_key(gb.w);
+            uint32_t lo = gk[0], hi = gk[0];
 #pragma unroll
-            for (int g = 0; g < kNG; ++g) v[g] = gmax[tid * kNG + g];
-            sort32_desc(v);
-            float th = v[0];
+            for (int m = 1; m < 8; ++m) {
+                lo = min(lo, gk[m]);
+                hi = max(hi, gk[m]);
+            }
+            lo = grp8_min(lo);
+            hi = grp8_max(hi);
+            // keys share the bits above the highest bit where lo and hi differ
+            const int hb = lo == hi ? -1 : 31 - __clz(lo ^ hi);
+            uint32_t tau = hb < 0 ? lo : (hb == 31 ? 0u : hi & ~((2u << hb) - 1u));
+            const int hbw = (int)wave_max_u32((uint32_t)(hb + 1)) - 1;
+            for (int bit = hbw; bit >= 0; --bit) {   // largest tau with >= n_cand maxima at or above it
+                const uint32_t t2 = tau | (1u << bit);
+                int c = 0;
 #pragma unroll
-            for (int g = 0; g < kNG; ++g)
-                if (g == n_cand - 1) th = v[g];
-            theta[tid] = bad[tid] ? 0xFFFFFFFFu : order_key(th);
+                for (int m = 0; m < 8; ++m) c += gk[m] >= t2 ? 1 : 0;
+                c = grp8_sum(c);
+                tau = c >= n_cand ? t2 : tau;
+            }
+            if (g == 0) theta[s] = bad[s] ? 0xFFFFFFFFu : tau;
         }
         __syncthreads();
         // ---- candidates above the threshold, into private slots ----
