@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6_000_000)
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-scene batched comparator")
     ap.add_argument("--no-sweep", action="store_true", help="skip the tolerance / CSC storage sweep")
+    ap.add_argument("--proposer-weights", default=None,
+                    help="FP32 parameter file (.npy): loaded instead of training when it exists, else written "
+                         "after training (lets counter passes reuse the proposer a traced run trained)")
     ap.add_argument("--quick", action="store_true",
                     help="headline step only, then a 1 GiB device copy (profiling and counter calibration)")
     args = ap.parse_args()
@@ -133,9 +136,16 @@ def main():
     sup, cnt = trainer.omp_labels(h, Xtr_g, k, eps)
     prop = sc.proposer_create(d, 256, K)
     prop.set_params(I.mlp_init(I.rng_for(5), d, 256, K))
-    hist = trainer.train(prop, Xtr_g, sup, cnt, epochs=args.epochs, batch=1024, lr=3e-3, pos_weight=8.0, seed=1)
+    if args.proposer_weights and os.path.exists(args.proposer_weights):
+        prop.set_params(torch.from_numpy(np.load(args.proposer_weights, allow_pickle=False)))
+        hist = {"loss": [float("nan")]}
+        log(f"proposer weights loaded from {args.proposer_weights}")
+    else:
+        hist = trainer.train(prop, Xtr_g, sup, cnt, epochs=args.epochs, batch=1024, lr=3e-3, pos_weight=8.0, seed=1)
+        if args.proposer_weights:
+            np.save(args.proposer_weights, prop.get_params().cpu().numpy())
     train_s = time.perf_counter() - t1
-    log(f"proposer trained in {train_s:.1f} s, loss {hist['loss'][-1]:.4f}")
+    log(f"proposer ready in {train_s:.1f} s, loss {hist['loss'][-1]:.4f}")
     del Xtr_g, sup, cnt
     untrained = sc.proposer_create(d, 256, K)
     untrained.set_params(I.mlp_init(I.rng_for(5), d, 256, K))

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "sc_internal.h"
 
@@ -708,7 +709,7 @@ int sc_batch_autotune(const sc_scene *scenes, int n_scenes, int64_t sample, void
 
 namespace {
 struct TrainLayout {
-    size_t xh, a1, h1, a2, h2, z, dz, da2, da1, loss, total;
+    size_t xh, a1, h1, a2, h2, z, dz, da2, da1, loss, part, total;
 };
 TrainLayout train_layout(int64_t B, int K) {
     TrainLayout t;
@@ -729,6 +730,12 @@ TrainLayout train_layout(int64_t B, int K) {
     t.da2 = take(e * B * 256);
     t.da1 = take(e * B * 256);
     t.loss = take(sizeof(float));
+    // split-K partial tiles of the three weight-gradient products (reused in turn)
+    const int Bi = (int)B;
+    size_t np = 0;
+    for (const auto &mn : {std::pair<int, int>{K, 256}, {256, 256}, {256, 64}})
+        np = std::max(np, (size_t)sc::gemm_splits(mn.first, mn.second, Bi) * mn.first * mn.second);
+    t.part = take(sizeof(float) * np);
     t.total = o;
     return t;
 }
@@ -757,6 +764,7 @@ int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, i
     void *xh = w + L.xh, *h1 = w + L.h1, *h2 = w + L.h2, *dz = w + L.dz, *da2 = w + L.da2, *da1 = w + L.da1;
     float *a1 = (float *)(w + L.a1), *a2 = (float *)(w + L.a2), *z = (float *)(w + L.z);
     float *loss = (float *)(w + L.loss);
+    float *part = (float *)(w + L.part);
     const int d = p->d, H = p->H, K = p->K;
     // parameter and gradient views
     const float *W1 = p->params, *b1 = W1 + (size_t)H * d, *W2 = b1 + H, *b2 = W2 + (size_t)H * H, *W3 = b2 + H;
@@ -780,17 +788,17 @@ int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, i
     SC_HIP(sc::launch_gemm(g3, f32, st), fn);
     SC_HIP(sc::launch_bce_grad(z, B, K, rows, sup_idx, sup_count, kcap, pos_weight, dz, loss, f32, st), fn);
     // backward
-    GemmArgs gw3{K, H, (int)B, dz, 1, K, h2, H, 1, sc::EPI_STORE, H, nullptr, nullptr, gW3, H, nullptr, 0, nullptr};
+    GemmArgs gw3{K, H, (int)B, dz, 1, K, h2, H, 1, sc::EPI_STORE, H, nullptr, nullptr, gW3, H, nullptr, 0, nullptr, part};
     SC_HIP(sc::launch_gemm(gw3, f32, st), fn);
     SC_HIP(sc::launch_colsum(dz, B, K, K, gb3, f32, st), fn);
     GemmArgs gd2{(int)B, H, K, dz, K, 1, Wb3, H, 1, sc::EPI_DGELU, H, nullptr, a2, nullptr, H, da2, H, nullptr};
     SC_HIP(sc::launch_gemm(gd2, f32, st), fn);
-    GemmArgs gw2{H, H, (int)B, da2, 1, H, h1, H, 1, sc::EPI_STORE, H, nullptr, nullptr, gW2, H, nullptr, 0, nullptr};
+    GemmArgs gw2{H, H, (int)B, da2, 1, H, h1, H, 1, sc::EPI_STORE, H, nullptr, nullptr, gW2, H, nullptr, 0, nullptr, part};
     SC_HIP(sc::launch_gemm(gw2, f32, st), fn);
     SC_HIP(sc::launch_colsum(da2, B, H, H, gb2, f32, st), fn);
     GemmArgs gd1{(int)B, H, H, da2, H, 1, Wb2, H, 1, sc::EPI_DGELU, H, nullptr, a1, nullptr, H, da1, H, nullptr};
     SC_HIP(sc::launch_gemm(gd1, f32, st), fn);
-    GemmArgs gw1{H, 64, (int)B, da1, 1, H, xh, 64, 1, sc::EPI_STORE, d, nullptr, nullptr, gW1, d, nullptr, 0, nullptr};
+    GemmArgs gw1{H, 64, (int)B, da1, 1, H, xh, 64, 1, sc::EPI_STORE, d, nullptr, nullptr, gW1, d, nullptr, 0, nullptr, part};
     SC_HIP(sc::launch_gemm(gw1, f32, st), fn);
     SC_HIP(sc::launch_colsum(da1, B, H, H, gb1, f32, st), fn);
     if (grads_out)

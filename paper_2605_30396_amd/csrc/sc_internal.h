@@ -125,8 +125,12 @@ struct GemmArgs {
     void *Ch;              // activation output (BF16 or FP32 by mode, row stride ldh) or NULL
     int64_t ldh;
     float *Cpre;           // GELU: pre-activation output (row stride ldc)
+    float *part;           // split-K partial tiles (gemm_splits(M, N, K) * M * N floats) or NULL
 };
 
+// Number of K-slices of a STORE-epilogue product with few output tiles
+// (weight gradients); 1 = no split.
+int gemm_splits(int M, int N, int K);
 hipError_t launch_gemm(const GemmArgs &g, bool f32, hipStream_t st);
 hipError_t launch_train_prep(const float *X, const int32_t *rows, int64_t B, int d, void *xh, bool f32,
                              hipStream_t st);

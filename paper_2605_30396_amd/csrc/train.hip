@@ -7,11 +7,17 @@
 //   STORE  C = acc (+ bias)
 //   GELU   a = acc + bias is saved, h = GELU(a) is the next layer's input
 //   DGELU  C = acc * GELU'(a_saved)          (backprop through the activation)
+// Products with few output tiles and a long reduction (the weight gradients,
+// reduced over the batch) are split along K: each slice writes its partial
+// tile to a workspace and a second kernel adds the slices in a fixed order
+// and applies the epilogue, so the result stays deterministic.
 // Two precisions: BF16 operands on v_mfma_f32_32x32x16_bf16 (production: the
 // same rounding points as the inference kernel), or FP32 operands on
 // v_mfma_f32_32x32x2_f32 (used to check the gradients against the FP64
 // oracle).  Operands are addressed with arbitrary element strides so the
 // transposed products of the backward pass need no copies.
+#include <algorithm>
+
 #include "mfma.h"
 #include "sc_internal.h"
 #include "wave.h"
@@ -25,11 +31,12 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmArgs g) {
     const int lane = threadIdx.x;
     const int n0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
     const int lr = lane & 31, lh = lane >> 5;
+    const int kspan = g.K / (int)gridDim.z, kbeg = blockIdx.z * kspan, kend = kbeg + kspan;
     floatx16 acc = floatx16{};
     if (F32) {
         const float *A = (const float *)g.A;
         const float *B = (const float *)g.B;
-        for (int k0 = 0; k0 < g.K; k0 += 2) {
+        for (int k0 = kbeg; k0 < kend; k0 += 2) {
             const float a = A[(int64_t)(m0 + lr) * g.sam + (int64_t)(k0 + lh) * g.sak];
             const float b = B[(int64_t)(k0 + lh) * g.sbk + (int64_t)(n0 + lr) * g.sbn];
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
@@ -37,7 +44,7 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmArgs g) {
     } else {
         const uint16_t *A = (const uint16_t *)g.A;
         const uint16_t *B = (const uint16_t *)g.B;
-        for (int k0 = 0; k0 < g.K; k0 += 16) {
+        for (int k0 = kbeg; k0 < kend; k0 += 16) {
             bf16x8 a, b;
             if (g.sak == 1) {
                 a = ld_bf16x8(A + (int64_t)(m0 + lr) * g.sam + k0 + 8 * lh);
@@ -57,6 +64,12 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmArgs g) {
         }
     }
     const int j = n0 + lr;
+    if (gridDim.z > 1) {   // split-K slice: raw partial tile, epilogue after the reduction
+        float *P = g.part + (size_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) P[(size_t)(m0 + 8 * (r >> 2) + 4 * lh + (r & 3)) * g.N + j] = acc[r];
+        return;
+    }
     if (j >= g.Nvalid) return;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -81,13 +94,40 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmArgs g) {
     }
 }
 
+// C = sum over slices of the partial tiles (+ bias), STORE epilogue.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int S) {
+    const int64_t mn = (int64_t)g.M * g.N;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < mn; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t / g.N), j = (int)(t - (int64_t)i * g.N);
+        if (j >= g.Nvalid) continue;
+        float v = 0.f;
+        for (int s = 0; s < S; ++s) v += g.part[(size_t)s * mn + t];
+        if (g.bias) v += g.bias[j];
+        g.Cf[(int64_t)i * g.ldc + j] = v;
+    }
+}
+
+int gemm_splits(int M, int N, int K) {
+    const int tiles = (M / 32) * (N / 32);
+    int s = 1;
+    while (tiles * s < 512 && K % (32 * s) == 0 && K / (2 * s) >= 64) s *= 2;
+    return s;
+}
+
 hipError_t launch_gemm(const GemmArgs &g, bool f32, hipStream_t st) {
     if (g.M % 32 || g.N % 32 || g.K % 16) return hipErrorInvalidValue;
-    dim3 grid(g.N / 32, g.M / 32);
+    int S = 1;
+    if (g.part && g.epi == EPI_STORE && g.Cf && !g.Ch) S = gemm_splits(g.M, g.N, g.K);
+    dim3 grid(g.N / 32, g.M / 32, S);
     if (f32)
         hipLaunchKernelGGL(gemm_kernel<true>, grid, dim3(64), 0, st, g);
     else
         hipLaunchKernelGGL(gemm_kernel<false>, grid, dim3(64), 0, st, g);
+    if (S > 1) {
+        const int64_t mn = (int64_t)g.M * g.N;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)std::min<int64_t>((mn + 255) / 256, 1024)), dim3(256),
+                           0, st, g, S);
+    }
     return hipGetLastError();
 }
 
@@ -110,14 +150,20 @@ __global__ void train_prep_kernel(const float *__restrict__ X, const int32_t *__
 }
 
 // dz = (w y (sigma(z) - 1) + (1 - y) sigma(z)) / (B K), y = multi-hot OMP support;
-// loss accumulated into *loss (mean over the B K entries).
+// loss accumulated into *loss (mean over the B K entries).  Grid-stride over
+// the B K entries with a bounded grid, so the loss takes one atomic per block.
+constexpr int kBceBlocks = 1024;
 template <bool F32>
-__global__ void bce_grad_kernel(const float *__restrict__ Z, int64_t B, int K, const int32_t *__restrict__ rows,
-                                const int32_t *__restrict__ sup, const int32_t *__restrict__ cnt, int kcap,
-                                float pos_weight, void *__restrict__ dz, float *__restrict__ loss) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void bce_grad_kernel(const float *__restrict__ Z, int64_t B, int K,
+                                                       const int32_t *__restrict__ rows,
+                                                       const int32_t *__restrict__ sup,
+                                                       const int32_t *__restrict__ cnt, int kcap, float pos_weight,
+                                                       void *__restrict__ dz, float *__restrict__ loss) {
+    __shared__ float part[4];
+    const int64_t n = B * K;
+    const float inv = 1.f / ((float)B * (float)K);
     float l = 0.f;
-    if (t < B * K) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = t / K;
         const int j = (int)(t - b * K);
         const int64_t r = rows ? (int64_t)rows[b] : b;
@@ -127,13 +173,12 @@ __global__ void bce_grad_kernel(const float *__restrict__ Z, int64_t B, int K, c
         const float z = Z[t];
         const float sp = fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z)));   // softplus(z)
         const float sig = 1.f / (1.f + __expf(-z));
-        const float inv = 1.f / ((float)B * (float)K);
         float g;
         if (y) {
-            l = pos_weight * (sp - z);
+            l += pos_weight * (sp - z);
             g = pos_weight * (sig - 1.f) * inv;
         } else {
-            l = sp;
+            l += sp;
             g = sig * inv;
         }
         if (F32)
@@ -143,19 +188,39 @@ __global__ void bce_grad_kernel(const float *__restrict__ Z, int64_t B, int K, c
     }
     if (loss) {
         l = wave_sum(l);
-        if ((threadIdx.x & 63) == 0 && l != 0.f) atomicAdd(loss, l / ((float)B * (float)K));
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const float s = (part[0] + part[1]) + (part[2] + part[3]);
+            if (s != 0.f) atomicAdd(loss, s * inv);
+        }
     }
 }
 
-// out[j] = sum_i A[i * ld + j] over M rows (bias gradients).
+// out[j] = sum_i A[i * ld + j] over M rows (bias gradients).  One block per
+// 64 columns; its 16 waves take every 16th row, so 16 row streams are in
+// flight per column group, and the 16 partial sums are added in a fixed order
+// (deterministic result).
 template <bool F32>
-__global__ void colsum_kernel(const void *__restrict__ A, int64_t M, int N, int64_t ld, float *__restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+__global__ __launch_bounds__(1024) void colsum_kernel(const void *__restrict__ A, int64_t M, int N, int64_t ld,
+                                                      float *__restrict__ out) {
+    __shared__ float part[16][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int64_t i = 0; i < M; ++i)
-        s += F32 ? ((const float *)A)[i * ld + j] : bf16_to_f32(((const uint16_t *)A)[i * ld + j]);
-    out[j] = s;
+    if (j < N) {
+#pragma unroll 8
+        for (int64_t i = w; i < M; i += 16)
+            s += F32 ? ((const float *)A)[i * ld + j] : bf16_to_f32(((const uint16_t *)A)[i * ld + j]);
+    }
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < N) {
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += part[q][lane];
+        out[j] = t;
+    }
 }
 
 // Adam, in place on the FP32 master parameters (bias-corrected step sizes
@@ -187,7 +252,7 @@ hipError_t launch_bce_grad(const float *Z, int64_t B, int K, const int32_t *rows
                            const int32_t *cnt, int kcap, float pos_weight, void *dz, float *loss, bool f32,
                            hipStream_t st) {
     const int64_t n = B * K;
-    dim3 grid((unsigned)((n + 255) / 256));
+    dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, kBceBlocks));
     if (f32)
         hipLaunchKernelGGL(bce_grad_kernel<true>, grid, dim3(256), 0, st, Z, B, K, rows, sup, cnt, kcap, pos_weight, dz,
                            loss);
@@ -198,11 +263,11 @@ hipError_t launch_bce_grad(const float *Z, int64_t B, int K, const int32_t *rows
 }
 
 hipError_t launch_colsum(const void *A, int64_t M, int N, int64_t ld, float *out, bool f32, hipStream_t st) {
-    dim3 grid((N + 255) / 256);
+    dim3 grid((N + 63) / 64);
     if (f32)
-        hipLaunchKernelGGL(colsum_kernel<true>, grid, dim3(256), 0, st, A, M, N, ld, out);
+        hipLaunchKernelGGL(colsum_kernel<true>, grid, dim3(1024), 0, st, A, M, N, ld, out);
     else
-        hipLaunchKernelGGL(colsum_kernel<false>, grid, dim3(256), 0, st, A, M, N, ld, out);
+        hipLaunchKernelGGL(colsum_kernel<false>, grid, dim3(1024), 0, st, A, M, N, ld, out);
     return hipGetLastError();
 }
 
