@@ -366,7 +366,16 @@ def main():
                 "ms_colour_step": round(t_col, 4), "mean_atoms": round(nnz / N2, 3),
                 "compression_ratio": round(storage.compression_ratio(N2, nnz, K2), 3),
                 "rel_sh_error": round(float(torch.linalg.vector_norm(r2.double()).item()) / x2n, 5)})
-        log(f"tolerance sweep in {time.perf_counter() - t_s:.1f} s: {sweep['points']}")
+        # the dictionary half of one learning pass (MOD from the tol = 0.1 codes), and the encoder
+        # writing CSC directly at that tolerance
+        i2, c2, n2, r2 = sc.omp_encode(h2, X2, k2, 0.1, sc.EPS_RELATIVE)
+        t_mod, (_, nrep) = evt(lambda: sc.mod_update(X2, i2, c2, n2, r2, K2))
+        t_csc, _ = evt(lambda: sc.omp_encode_csc(h2, X2, k2, 0.1, sc.EPS_RELATIVE))
+        sweep["mod_update"] = {"ms": round(t_mod, 3), "atoms_replaced": int(nrep), "N": N2, "K": K2,
+                               "codes": "tol 0.1, k 32"}
+        sweep["encode_csc_tol0.1_ms"] = round(t_csc, 3)
+        log(f"tolerance sweep in {time.perf_counter() - t_s:.1f} s: {sweep['points']}, MOD {t_mod:.2f} ms, "
+            f"encode to CSC {t_csc:.2f} ms")
         h2.destroy()
         del X2, pos2, dc2
 

@@ -150,8 +150,11 @@ __global__ void train_prep_kernel(const float *__restrict__ X, const int32_t *__
 }
 
 // dz = (w y (sigma(z) - 1) + (1 - y) sigma(z)) / (B K), y = multi-hot OMP support;
-// loss accumulated into *loss (mean over the B K entries).  Grid-stride over
-// the B K entries with a bounded grid, so the loss takes one atomic per block.
+// loss accumulated into *loss (mean over the B K entries).  A wave takes 64
+// consecutive logits of one row (K is a multiple of 64): lane q < count holds
+// the row's q-th support atom and the membership test reads it by lane index.
+// Waves stride over the B K / 64 chunks with a bounded grid, so the loss takes
+// one atomic per block.
 constexpr int kBceBlocks = 1024;
 template <bool F32>
 __global__ __launch_bounds__(256) void bce_grad_kernel(const float *__restrict__ Z, int64_t B, int K,
@@ -160,16 +163,19 @@ __global__ __launch_bounds__(256) void bce_grad_kernel(const float *__restrict__
                                                        const int32_t *__restrict__ cnt, int kcap, float pos_weight,
                                                        void *__restrict__ dz, float *__restrict__ loss) {
     __shared__ float part[4];
-    const int64_t n = B * K;
+    const int lane = threadIdx.x & 63;
+    const int64_t nchunk = B * K / 64;
     const float inv = 1.f / ((float)B * (float)K);
     float l = 0.f;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = t / K;
+    for (int64_t ch = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); ch < nchunk; ch += (int64_t)gridDim.x * 4) {
+        const int64_t t = ch * 64 + lane;
+        const int64_t b = (ch * 64) / K;
         const int j = (int)(t - b * K);
         const int64_t r = rows ? (int64_t)rows[b] : b;
         const int c = min(max(cnt[r], 0), kcap);
+        const int myatom = lane < c ? sup[r * kcap + lane] : -1;
         bool y = false;
-        for (int q = 0; q < c; ++q) y |= sup[r * kcap + q] == j;
+        for (int q = 0; q < c; ++q) y |= __shfl(myatom, q, 64) == j;
         const float z = Z[t];
         const float sp = fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z)));   // softplus(z)
         const float sig = 1.f / (1.f + __expf(-z));
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(256) void bce_grad_kernel(const float *__restrict__
     }
     if (loss) {
         l = wave_sum(l);
-        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+        if (lane == 0) part[threadIdx.x >> 6] = l;
         __syncthreads();
         if (threadIdx.x == 0) {
             const float s = (part[0] + part[1]) + (part[2] + part[3]);
@@ -251,6 +257,7 @@ hipError_t launch_train_prep(const float *X, const int32_t *rows, int64_t B, int
 hipError_t launch_bce_grad(const float *Z, int64_t B, int K, const int32_t *rows, const int32_t *sup,
                            const int32_t *cnt, int kcap, float pos_weight, void *dz, float *loss, bool f32,
                            hipStream_t st) {
+    if (K % 64) return hipErrorInvalidValue;
     const int64_t n = B * K;
     dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, kBceBlocks));
     if (f32)
