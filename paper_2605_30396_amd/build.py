@@ -28,13 +28,23 @@ CXXFLAGS = [
 ]
 
 
+# Kernels whose MFMA accumulators live only through the correlation stage:
+# VGPR-form MFMA lets the pursuit reuse those registers (accumulation
+# registers would stay allocated for the whole kernel and cost a wave per SIMD).
+EXTRA = {
+    "omp_batch_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "omp_batch_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "omp_multi.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = ["hipcc", *CXXFLAGS, "-c", src, "-o", obj]
+    cmd = ["hipcc", *CXXFLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # the host pass does not know the GPU feature flag; that warning is expected
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)

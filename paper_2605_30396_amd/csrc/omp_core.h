@@ -41,10 +41,16 @@ constexpr int kXhs = 72;                              // LDS row stride (BF16) o
 constexpr uint32_t kKeyIdx = 1023u;                   // atom index bits of a selection key
 constexpr uint32_t kKeyMag = 0x7FFFFFFFu & ~kKeyIdx;  // magnitude bits of a selection key
 
-// LDS bytes of one workgroup: alpha0 tile [T][Kp], signal tile [64][T], and
-// for the split-BF16 correlations the two BF16 signal parts [T][kXhs].
+// Row stride (floats) of the alpha0 tile in LDS: 4 floats past Kp, so the
+// 16 rows an MFMA result writes at once start 16 bytes apart and spread over
+// the banks instead of hitting the same ones.
+__host__ __device__ constexpr int a0_stride(int Kp) { return Kp + 4; }
+
+// LDS bytes of one workgroup: alpha0 tile [T][a0_stride(Kp)], signal tile
+// [64][T], and for the split-BF16 correlations the two BF16 signal parts
+// [T][kXhs].
 __host__ __device__ constexpr size_t omp_tile_lds(int T, int Kp, bool split) {
-    return sizeof(float) * ((size_t)T * Kp + 64 * (size_t)T) + (split ? sizeof(uint16_t) * 2 * T * kXhs : 0);
+    return sizeof(float) * ((size_t)T * a0_stride(Kp) + 64 * (size_t)T) + (split ? sizeof(uint16_t) * 2 * T * kXhs : 0);
 }
 
 struct OmpTally {
@@ -73,7 +79,10 @@ __device__ __forceinline__ void load_tile(const OmpParams &p, int d, int64_t s0,
     }
 }
 
-// alpha0 tile on VALU: A0[s][j] = sum_i DT[i][j] Xt[i][s].
+// alpha0 tile on VALU: A0[s][j] = sum_i DT[i][j] Xt[i][s].  The dictionary
+// rows are read from L2 four features ahead of their use (a ring of four row
+// slices in registers), so the L2 latency overlaps the FMAs of the features
+// in between instead of stalling every feature.
 template <int E, int T>
 __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d, const float *__restrict__ Xt,
                                             float *__restrict__ A0, int tid) {
@@ -82,34 +91,62 @@ __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d,
     constexpr int SG = kOmpThreads / KpP;                      // signal groups
     constexpr int JS = Kp / KpP;                               // atom slots per thread
     constexpr int SQ = T / SG;                                 // signals per thread
+    constexpr int PF = 4;                                      // prefetch distance (features)
     static_assert(Kp % KpP == 0 && T % SG == 0, "tile shape");
     const int j0 = tid % KpP, sg = tid / KpP;
+    const float *__restrict__ dp = DT + j0;
     float acc[JS][SQ];
 #pragma unroll
     for (int r = 0; r < JS; ++r)
 #pragma unroll
         for (int q = 0; q < SQ; ++q) acc[r][q] = 0.f;
-    for (int i = 0; i < d; ++i) {
-        float dv[JS];
+    float ring[PF][JS];
 #pragma unroll
-        for (int r = 0; r < JS; ++r) dv[r] = DT[(size_t)i * Kp + j0 + r * KpP];
+    for (int u = 0; u < PF; ++u) {
+        const int i = u < d ? u : d - 1;
 #pragma unroll
-        for (int q = 0; q < SQ; ++q) {
-            const float xv = Xt[i * T + sg + q * SG];
+        for (int r = 0; r < JS; ++r) ring[u][r] = dp[(size_t)i * Kp + r * KpP];
+    }
+    for (int i0 = 0; i0 < d; i0 += PF) {
 #pragma unroll
-            for (int r = 0; r < JS; ++r) acc[r][q] = fmaf(dv[r], xv, acc[r][q]);
+        for (int u = 0; u < PF; ++u) {
+            const int i = i0 + u;
+            if (i < d) {
+                float xv[SQ];
+                if constexpr (SG == 1 && SQ % 4 == 0) {
+#pragma unroll
+                    for (int q4 = 0; q4 < SQ / 4; ++q4) {
+                        const float4 v = *reinterpret_cast<const float4 *>(Xt + i * T + 4 * q4);
+                        xv[4 * q4] = v.x;
+                        xv[4 * q4 + 1] = v.y;
+                        xv[4 * q4 + 2] = v.z;
+                        xv[4 * q4 + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < SQ; ++q) xv[q] = Xt[i * T + sg + q * SG];
+                }
+#pragma unroll
+                for (int q = 0; q < SQ; ++q)
+#pragma unroll
+                    for (int r = 0; r < JS; ++r) acc[r][q] = fmaf(ring[u][r], xv[q], acc[r][q]);
+                const int inext = i + PF < d ? i + PF : d - 1;
+#pragma unroll
+                for (int r = 0; r < JS; ++r) ring[u][r] = dp[(size_t)inext * Kp + r * KpP];
+            }
         }
     }
 #pragma unroll
     for (int r = 0; r < JS; ++r)
 #pragma unroll
-        for (int q = 0; q < SQ; ++q) A0[(sg + q * SG) * Kp + j0 + r * KpP] = acc[r][q];
+        for (int q = 0; q < SQ; ++q) A0[(sg + q * SG) * a0_stride(Kp) + j0 + r * KpP] = acc[r][q];
 }
 
 // alpha0 tile on FP32 MFMA (v_mfma_f32_16x16x4_f32): wave w computes the
 // 16-atom blocks w, w+4, ... for every 16-signal column block.  A operand:
-// 16 atoms x 4 features read from the feature-major dictionary; B operand:
-// 4 features x 16 signals from the LDS signal tile.
+// 16 atoms x 4 features read from the feature-major dictionary, one k-step
+// ahead of its use; B operand: 4 features x 16 signals from the LDS signal
+// tile.
 template <int E, int T>
 __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ DT, int d, const float *__restrict__ Xt,
                                                 float *__restrict__ A0, int wave, int lane) {
@@ -122,25 +159,38 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ DT, in
 #pragma unroll
         for (int c = 0; c < CB; ++c) acc[b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int dk = (d + 3) & ~3;
-#pragma unroll 2
+    float an[NB];
+    {
+        const int f = kq;
+        const float *row = DT + (size_t)(f < d ? f : 0) * Kp + lr;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) an[b] = f < d ? row[(wave + kOmpWaves * b) * 16] : 0.f;
+    }
     for (int k0 = 0; k0 < dk; k0 += 4) {
+        float a[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) a[b] = an[b];
+        {
+            const int f = k0 + 4 + kq;
+            const float *row = DT + (size_t)(f < d ? f : 0) * Kp + lr;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) an[b] = f < d ? row[(wave + kOmpWaves * b) * 16] : 0.f;
+        }
         const int f = k0 + kq;
         float bx[CB];
 #pragma unroll
         for (int c = 0; c < CB; ++c) bx[c] = Xt[f * T + c * 16 + lr];
-        const float *row = DT + (size_t)(f < d ? f : 0) * Kp + lr;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const float a = f < d ? row[(wave + kOmpWaves * b) * 16] : 0.f;
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int c = 0; c < CB; ++c) acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bx[c], acc[b][c], 0, 0, 0);
-        }
+            for (int c = 0; c < CB; ++c) acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b], bx[c], acc[b][c], 0, 0, 0);
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-            *reinterpret_cast<floatx4 *>(A0 + (c * 16 + lr) * Kp + (wave + kOmpWaves * b) * 16 + 4 * kq) = acc[b][c];
+            *reinterpret_cast<floatx4 *>(A0 + (c * 16 + lr) * a0_stride(Kp) + (wave + kOmpWaves * b) * 16 + 4 * kq) =
+                acc[b][c];
 }
 
 // alpha0 tile (16 signals) as the split BF16 product Dh xh + Dl xh + Dh xl,
@@ -170,7 +220,7 @@ __device__ __forceinline__ void alpha0_mfma_bf16x3(const uint16_t *__restrict__ 
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-        *reinterpret_cast<floatx4 *>(A0 + lr * Kp + (wave + kOmpWaves * b) * 16 + 4 * kq) = acc[b];
+        *reinterpret_cast<floatx4 *>(A0 + lr * a0_stride(Kp) + (wave + kOmpWaves * b) * 16 + 4 * kq) = acc[b];
 }
 
 // The E Gram-row entries of this lane (16-byte aligned for E % 4 == 0).
@@ -237,7 +287,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     for (int e = 0; e < E; ++e) {
         const int j = lane * E + e;
         const bool real = j < K;
-        a0[e] = real ? A0[s * Kp + j] : 0.f;
+        a0[e] = real ? A0[s * a0_stride(Kp) + j] : 0.f;
         msk[e] = real ? kKeyMag : 0u;
         kid[e] = kKeyIdx - (uint32_t)j;
     }
@@ -367,7 +417,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         if constexpr (kSplit)
             zj = wave_sum(lane < d ? Dg[(size_t)j * d + lane] * xv : 0.f);
         else
-            zj = A0[s * Kp + j];
+            zj = A0[s * a0_stride(Kp) + j];
         const float cn = (zj - wc) * inv;
         rr = fmaf(-cn, cn, rr);
         lmax = fmaxf(lmax, ell);
@@ -414,7 +464,7 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
                                          unsigned char *smem, int tid, OmpTally &tally) {
     constexpr int Kp = 64 * E;
     float *A0 = reinterpret_cast<float *>(smem);
-    float *Xt = A0 + T * Kp;
+    float *Xt = A0 + T * a0_stride(Kp);
     const int lane = tid & 63, wave = tid >> 6;
     __syncthreads();   // the previous tile is done with Xt and A0
     load_tile<T>(p, dict.d, s0, nt, Xt, tid);

@@ -20,6 +20,7 @@ namespace sc {
 
 constexpr int kRCpl = 4;           // candidates per lane (n_cand <= 32)
 constexpr int kRThreads = 256;
+constexpr int kMissQ = 128;        // fallback rows queued per wave before one atomic reserves their slots
 
 template <int KMAX>
 struct GroupScratch {
@@ -28,6 +29,7 @@ struct GroupScratch {
     float gam[KMAX];
     int sel[KMAX];
     float x[48];
+    int cand[8 * kRCpl];
 };
 
 template <int KMAX>
@@ -74,15 +76,37 @@ __device__ __forceinline__ void grp_back_substitute(GroupScratch<KMAX> &gs, int 
 }
 
 // ||x - D_I gamma||^2 over the group (lane g holds features g, g+8, ...).
-template <int KMAX>
+// The atom rows are read in batches of BT steps with every load of a batch in
+// flight at once (steps past n read atom 0 with a zero weight).
+template <int KMAX, int BT>
 __device__ __forceinline__ float grp_resid2(const GroupScratch<KMAX> &gs, int n, const float *__restrict__ D48, int d,
                                             int g) {
-    float acc = 0.f;
-    for (int f = g; f < d; f += 8) {
-        float r = gs.x[f];
-        for (int t = 0; t < n; ++t) r -= D48[(size_t)gs.sel[t] * 48 + f] * gs.gam[t];
-        acc = fmaf(r, r, acc);
+    float r[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) r[q] = gs.x[g + 8 * q];   // zero beyond d
+#pragma unroll
+    for (int t0 = 0; t0 < KMAX; t0 += BT) {
+        if (__ballot(t0 < n) != 0) {   // some active group still has steps here
+            float a[BT][6], gt[BT];
+#pragma unroll
+            for (int u = 0; u < BT; ++u) {
+                const int t = t0 + u;
+                const bool on = t < n;
+                const int j = on ? gs.sel[t < KMAX ? t : 0] : 0;
+                gt[u] = on ? gs.gam[t < KMAX ? t : 0] : 0.f;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) a[u][q] = D48[(size_t)j * 48 + g + 8 * q];
+            }
+#pragma unroll
+            for (int u = 0; u < BT; ++u)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) r[q] = fmaf(-a[u][q], gt[u], r[q]);
+        }
     }
+    float acc = 0.f;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc = fmaf(r[q], r[q], acc);
+    (void)d;
     return grp_sum(acc);
 }
 
@@ -99,6 +123,20 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
     const float *__restrict__ G = dict.G;
     const float nanv = __builtin_nanf("");
     unsigned long long n_sig = 0, n_atoms = 0, n_miss = 0, n_refit = 0;
+    // per-wave queue of fallback rows (wave-uniform fill level nq)
+    __shared__ int32_t miss_queue[kRThreads / 64][kMissQ];
+    int32_t *mq = miss_queue[wave];
+    int nq = 0;
+    auto flush_misses = [&]() {
+        if (nq == 0) return;
+        __builtin_amdgcn_wave_barrier();
+        int base = 0;
+        if (lane == 0) base = atomicAdd(p.miss_count, nq);
+        base = __builtin_amdgcn_readfirstlane(base);
+        for (int q = lane; q < nq; q += 64) p.miss_rows[base + q] = mq[q];
+        __builtin_amdgcn_wave_barrier();
+        nq = 0;
+    };
     using vR = vecr<kRCpl>;
 
     const int64_t ngroups = (p.N + 7) / 8;
@@ -107,44 +145,75 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
     for (int64_t wg = gwave; wg < ngroups; wg += wstride) {
         const int64_t sig = wg * 8 + grp;
         const bool valid = sig < p.N;
-        // ---- signal and candidates ----
+        // ---- signal and candidates: every load issued before the first use ----
+        float xr[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int f = g + 8 * q;
+            xr[q] = (valid && f < d) ? p.X[sig * d + f] : 0.f;
+        }
+        int cid[kRCpl];
+#pragma unroll
+        for (int e = 0; e < kRCpl; ++e) {
+            const int q = g * kRCpl + e;
+            cid[e] = (valid && q < nc) ? p.cand[sig * nc + q] : -1;
+        }
+        const int first = valid ? p.cand[sig * nc] : 0;
         float xx_part = 0.f;
         bool fin = true;
-        for (int f = g; f < 48; f += 8) {
-            float v = (valid && f < d) ? p.X[sig * d + f] : 0.f;
-            fin &= isfinite(v);
-            gs.x[f] = v;
-            xx_part = fmaf(v, v, xx_part);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            fin &= isfinite(xr[q]);
+            gs.x[g + 8 * q] = xr[q];
+            xx_part = fmaf(xr[q], xr[q], xx_part);
         }
         int nf = fin ? 0 : 1;
         nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_QP1032, 0xF, 0xF, false);
         nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_QP2301, 0xF, 0xF, false);
         nf |= __builtin_amdgcn_update_dpp(0, nf, SC_DPP_HMIRROR, 0xF, 0xF, false);
         const float xx = grp_sum(xx_part);
-        int cid[kRCpl];
-        bool cand_ok = true;
-#pragma unroll
-        for (int e = 0; e < kRCpl; ++e) {
-            const int q = g * kRCpl + e;
-            cid[e] = (valid && q < nc) ? p.cand[sig * nc + q] : -1;
-        }
-        {
-            int first = valid ? p.cand[sig * nc] : 0;
-            cand_ok = first >= 0;
-        }
+        const bool cand_ok = first >= 0;
         __builtin_amdgcn_wave_barrier();
         // ---- alpha0 over the candidates ----
+        // Lane g takes features 6g .. 6g+5 of every candidate, so the group's
+        // eight lanes read one contiguous 192-byte dictionary row together
+        // (scattered per-lane rows cost one cache-line access per lane); the
+        // partial dots are summed over the group and each candidate's sum is
+        // kept by the lane that owns it in the pursuit.
+#pragma unroll
+        for (int e = 0; e < kRCpl; ++e) gs.cand[g * kRCpl + e] = cid[e];
+        __builtin_amdgcn_wave_barrier();
+        float xg[6];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float2 v = *reinterpret_cast<const float2 *>(gs.x + 6 * g + 2 * q);
+            xg[2 * q] = v.x;
+            xg[2 * q + 1] = v.y;
+        }
         vR al;
 #pragma unroll
         for (int e = 0; e < kRCpl; ++e) al[e] = 0.f;
-#pragma unroll 2
-        for (int f4 = 0; f4 < 12; ++f4) {
-            const float4 xv = *reinterpret_cast<const float4 *>(gs.x + 4 * f4);
+        constexpr int kCB = 4;   // candidates per batch of loads
+        static_assert((8 * kRCpl) % kCB == 0, "candidate batches");
 #pragma unroll
-            for (int e = 0; e < kRCpl; ++e) {
-                const int c = cid[e] < 0 ? 0 : cid[e];
-                const float4 dv = *reinterpret_cast<const float4 *>(D48 + (size_t)c * 48 + 4 * f4);
-                al[e] = fmaf(dv.x, xv.x, fmaf(dv.y, xv.y, fmaf(dv.z, xv.z, fmaf(dv.w, xv.w, al[e]))));
+        for (int b = 0; b < 8 * kRCpl / kCB; ++b) {
+            if (kCB * b >= nc) break;   // uniform: slots past the list are -1 (NaN below)
+            float2 dv[kCB][3];
+#pragma unroll
+            for (int u = 0; u < kCB; ++u) {
+                const int c = gs.cand[kCB * b + u];
+                const float2 *row = reinterpret_cast<const float2 *>(D48 + (size_t)(c < 0 ? 0 : c) * 48 + 6 * g);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) dv[u][q] = row[q];
+            }
+#pragma unroll
+            for (int u = 0; u < kCB; ++u) {
+                float part = 0.f;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) part = fmaf(dv[u][q].y, xg[2 * q + 1], fmaf(dv[u][q].x, xg[2 * q], part));
+                part = grp_sum(part);
+                const int cq = kCB * b + u;   // owned by lane cq / kRCpl, entry cq % kRCpl
+                if (g == cq / kRCpl) al[cq % kRCpl] = part;
             }
         }
 #pragma unroll
@@ -173,7 +242,7 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
                         go = false;
                     } else if (rr <= eps2 + band) {
                         grp_back_substitute<KMAX>(gs, it, g);
-                        float re = grp_resid2<KMAX>(gs, it, D48, d, g);
+                        float re = grp_resid2<KMAX, 2>(gs, it, D48, d, g);
                         if (re <= eps2) {
                             explicit_done = true;
                             rr_expl = re;
@@ -311,9 +380,11 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
             if (g == 0) n_refit += 1;
         }
         float re = 3.4e38f;
-        if (__ballot(need && !explicit_done) != 0) re = grp_resid2<KMAX>(gs, need ? n : 0, D48, d, g);
+        if (__ballot(need && !explicit_done) != 0) re = grp_resid2<KMAX, 4>(gs, need ? n : 0, D48, d, g);
         if (explicit_done) re = rr_expl;
         if (!need) re = 3.4e38f;
+        const bool accept = valid && !nf && cand_ok && (re <= eps2 || xx == 0.f);
+        const bool miss = valid && !nf && !accept;
         if (valid) {
             int32_t *oidx = p.idx + sig * k;
             float *ocoef = p.coef + sig * k;
@@ -326,7 +397,7 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
                     p.count[sig] = -1;
                     if (p.resid) p.resid[sig] = nanv;
                 }
-            } else if (cand_ok && (re <= eps2 || xx == 0.f)) {
+            } else if (accept) {
                 for (int t = g; t < k; t += 8) {
                     oidx[t] = t < n ? gs.sel[t] : -1;
                     ocoef[t] = t < n ? gs.gam[t] : 0.f;
@@ -337,19 +408,33 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
                     n_sig += 1;
                     n_atoms += n;
                 }
-            } else if (g == 0) {
-                const int pos = atomicAdd(p.miss_count, 1);
-                p.miss_rows[pos] = (int32_t)sig;
+            }
+        }
+        // misses of the wave's 8 signals are queued in LDS; the queue is
+        // flushed to the fallback list with one atomic per kMissQ entries
+        const uint64_t mb = __ballot(miss && g == 0);
+        if (mb) {
+            const int cm = __popcll(mb);
+            if (nq + cm > kMissQ) flush_misses();
+            if (miss && g == 0) {
+                mq[nq + __popcll(mb & ((1ull << lane) - 1ull))] = (int32_t)sig;
                 n_miss += 1;
             }
+            nq += cm;
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (p.stats && g == 0 && (n_sig | n_miss | n_refit)) {
-        atomicAdd(p.stats + 0, n_sig);
-        atomicAdd(p.stats + 1, n_atoms);
-        if (n_refit) atomicAdd(p.stats + 2, n_refit);
-        if (n_miss) atomicAdd(p.stats + 3, n_miss);
+    flush_misses();
+    if (p.stats) {   // one atomic per counter and wave
+        const unsigned long long v[4] = {n_sig, n_atoms, n_refit, n_miss};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            unsigned int t = (unsigned int)v[c];
+            t += __shfl_xor(t, 8);
+            t += __shfl_xor(t, 16);
+            t += __shfl_xor(t, 32);
+            if (lane == 0 && t) atomicAdd(p.stats + c, (unsigned long long)t);
+        }
     }
 }
 

@@ -510,7 +510,8 @@ int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, i
     const int kcap = h->restricted_cap > 0 ? std::min(h->restricted_cap, k) : k;
     sc::RompParams rp{X, N, k, eps, rel, refit, kKappaMax, kcap, cand, n_cand, idx, coef, count, resid, miss_rows,
                       miss_count, h->stats};
-    SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, kmax, st), "sc_omp_encode_learned (restricted)");
+    // the restricted pursuit never takes more than kcap steps: size its registers for that
+    SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, sc::pick_kmax(kcap), st), "sc_omp_encode_learned (restricted)");
     sc::OmpParams fp{X, N, miss_rows, miss_count, k, eps, rel, refit, kKappaMax, idx, coef, count, resid, h->stats};
     const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
     SC_HIP(sc::launch_omp_batch(h->dev, fp, kmax, a0, h->row_cache, st), "sc_omp_encode_learned (fallback)");
@@ -534,7 +535,7 @@ int sc_omp_encode_restricted(sc_dict h, const float *X, int64_t N, int k, float 
     const int kcap = h->restricted_cap > 0 ? std::min(h->restricted_cap, k) : k;
     sc::RompParams rp{X, N, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0, (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax,
                       kcap, cand, n_cand, idx, coef, count, resid, miss_rows, miss_count, h->stats};
-    SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, sc::pick_kmax(k), st), "sc_omp_encode_restricted");
+    SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, sc::pick_kmax(kcap), st), "sc_omp_encode_restricted");
     return SC_OK;
 }
 
