@@ -25,29 +25,60 @@ struct ModWork {
     unsigned long long *key;   // argmax scratch
 };
 
-// One wave per signal: XAt[j_t] += gamma_t x, AAt[j_t][j_u] += gamma_t gamma_u.
-__global__ __launch_bounds__(256) void mod_accum_kernel(const float *__restrict__ X, int64_t N, int d, int K,
+// XAt[j_t] += gamma_t x and AAt[j_t][j_u] += gamma_t gamma_u, accumulated in
+// LDS: workgroup (b, s) owns rows [b R, b R + R) of both products (R (K + d)
+// FP64 values, at most 64 KB) and the s-th slice of the signals.  One
+// wave takes one signal at a time; only steps whose atom falls in the block
+// touch LDS (FP64 LDS atomics), and the block is added to the global
+// products once, at the end, so global atomics scale with the blocks rather
+// than with the n (d + n) updates of every signal.
+constexpr int kModLdsDoubles = 8192;   // 64 KB of FP64 per workgroup
+__host__ __device__ inline int mod_rows(int K, int d) { return max(1, kModLdsDoubles / (K + d)); }
+
+__global__ __launch_bounds__(1024) void mod_accum_kernel(const float *__restrict__ X, int64_t N, int d, int K,
                                                         const int32_t *__restrict__ idx,
                                                         const float *__restrict__ coef,
-                                                        const int32_t *__restrict__ count, int k, ModWork w) {
+                                                        const int32_t *__restrict__ count, int k, int nslices,
+                                                        ModWork w) {
+    extern __shared__ __align__(16) double sAcc[];
+    const int R = mod_rows(K, d);
+    const int blk = blockIdx.x / nslices, slice = blockIdx.x - blk * nslices;
+    const int r0 = blk * R, r1 = min(K, r0 + R), nr = r1 - r0;
+    double *sA = sAcc;                 // nr x K
+    double *sX = sAcc + (size_t)R * K; // nr x d
+    for (int q = threadIdx.x; q < R * K + R * d; q += blockDim.x) sAcc[q] = 0.0;
+    __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), nw = (int64_t)gridDim.x * 4;
-    for (int64_t i = gw; i < N; i += nw) {
+    const int64_t per = (N + nslices - 1) / nslices;
+    const int64_t i0 = (int64_t)slice * per, i1 = min<int64_t>(N, i0 + per);
+    for (int64_t i = i0 + (threadIdx.x >> 6); i < i1; i += blockDim.x >> 6) {
         int n = count[i];
+        const int jr = lane < k ? idx[i * k + lane] : -1;   // issued with the count, not after it
         n = n < 0 ? 0 : (n > k ? k : n);
-        if (n == 0) continue;
+        const int jl = lane < n ? jr : -1;
+        const bool mine = jl >= r0 && jl < r1;
+        if (__ballot(mine) == 0) continue;   // no step of this signal falls in the block
         const double xv = lane < d ? (double)X[i * d + lane] : 0.0;
-        const int jl = lane < n ? idx[i * k + lane] : 0;
         const double gl = lane < n ? (double)coef[i * k + lane] : 0.0;
-        for (int t = 0; t < n; ++t) {
-            const int jt = __shfl(jl, t, 64);
+        const bool okl = jl >= 0 && jl < K;
+        uint64_t own = __ballot(mine);
+        while (own) {
+            const int t = __ffsll((unsigned long long)own) - 1;
+            own &= own - 1;
+            const int jt = __shfl(jl, t, 64) - r0;
             const double gt = __shfl(gl, t, 64);
-            if (jt < 0 || jt >= K) continue;
-            if (lane < d) atomicAdd(&w.XAt[(size_t)jt * d + lane], gt * xv);
-            if (lane < n) {
-                if (jl >= 0 && jl < K) atomicAdd(&w.AAt[(size_t)jt * K + jl], gt * gl);
-            }
+            if (lane < d) atomicAdd(&sX[(size_t)jt * d + lane], gt * xv);
+            if (lane < n && okl) atomicAdd(&sA[(size_t)jt * K + jl], gt * gl);
         }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nr * K; q += blockDim.x) {
+        const double v = sA[q];
+        if (v != 0.0) atomicAdd(&w.AAt[(size_t)r0 * K + q], v);
+    }
+    for (int q = threadIdx.x; q < nr * d; q += blockDim.x) {
+        const double v = sX[q];
+        if (v != 0.0) atomicAdd(&w.XAt[(size_t)r0 * d + q], v);
     }
 }
 
@@ -79,42 +110,50 @@ __global__ __launch_bounds__(1024) void mod_solve_kernel(int d, int K, ModWork w
     const double ridge = 1e-10 * tr / K;
     for (int j = threadIdx.x; j < K; j += blockDim.x) A[(size_t)j * K + j] += ridge;
     __syncthreads();
-    // left-looking Cholesky, column by column: A = L L^T in the lower triangle
+    // right-looking Cholesky, A = L L^T in the lower triangle: for each column,
+    // the pivot, the scaled column, then the trailing update spread over the
+    // whole workgroup
     for (int j = 0; j < K; ++j) {
-        double s = 0.0;
-        for (int p = threadIdx.x; p < j; p += blockDim.x) {
-            const double l = A[(size_t)j * K + p];
-            s += l * l;
-        }
-        s = block_sum_d(s, red);
         if (threadIdx.x == 0) {
-            const double v = A[(size_t)j * K + j] - s;
+            const double v = A[(size_t)j * K + j];
             diag_sh = sqrt(v > 1e-300 ? v : 1e-300);
             A[(size_t)j * K + j] = diag_sh;
         }
         __syncthreads();
-        const double ljj = diag_sh;
-        for (int i = j + 1 + threadIdx.x; i < K; i += blockDim.x) {
-            double v = A[(size_t)i * K + j];
-            for (int p = 0; p < j; ++p) v -= A[(size_t)i * K + p] * A[(size_t)j * K + p];
-            A[(size_t)i * K + j] = v / ljj;
+        const double rl = 1.0 / diag_sh;
+        for (int i = j + 1 + threadIdx.x; i < K; i += blockDim.x) A[(size_t)i * K + j] *= rl;
+        __syncthreads();
+        const int m = K - j - 1;   // trailing block (j+1 .. K-1), lower triangle incl. diagonal
+        for (int64_t q = threadIdx.x; q < (int64_t)m * m; q += blockDim.x) {
+            const int i = j + 1 + (int)(q / m), c = j + 1 + (int)(q % m);
+            if (c <= i) A[(size_t)i * K + c] -= A[(size_t)i * K + j] * A[(size_t)c * K + j];
         }
         __syncthreads();
     }
-    // L Z = XAt, then L^T Y = Z, one right-hand side (feature) per thread
-    for (int c = threadIdx.x; c < d; c += blockDim.x) {
-        for (int i = 0; i < K; ++i) {
-            double v = w.XAt[(size_t)i * d + c];
-            for (int p = 0; p < i; ++p) v -= A[(size_t)i * K + p] * w.Y[(size_t)p * d + c];
-            w.Y[(size_t)i * d + c] = v / A[(size_t)i * K + i];
-        }
-        for (int i = K - 1; i >= 0; --i) {
-            double v = w.Y[(size_t)i * d + c];
-            for (int p = i + 1; p < K; ++p) v -= A[(size_t)p * K + i] * w.Y[(size_t)p * d + c];
-            w.Y[(size_t)i * d + c] = v / A[(size_t)i * K + i];
-        }
-    }
+    // L Z = XAt, then L^T Y = Z, column-oriented: each step finishes one row of
+    // the d right-hand sides and updates the remaining rows in parallel
+    for (int q = threadIdx.x; q < K * d; q += blockDim.x) w.Y[q] = w.XAt[q];
     __syncthreads();
+    for (int p = 0; p < K; ++p) {
+        const double rl = 1.0 / A[(size_t)p * K + p];
+        for (int c = threadIdx.x; c < d; c += blockDim.x) w.Y[(size_t)p * d + c] *= rl;
+        __syncthreads();
+        for (int q = threadIdx.x; q < (K - p - 1) * d; q += blockDim.x) {
+            const int i = p + 1 + q / d, c = q % d;
+            w.Y[(size_t)i * d + c] -= A[(size_t)i * K + p] * w.Y[(size_t)p * d + c];
+        }
+        __syncthreads();
+    }
+    for (int p = K - 1; p >= 0; --p) {
+        const double rl = 1.0 / A[(size_t)p * K + p];
+        for (int c = threadIdx.x; c < d; c += blockDim.x) w.Y[(size_t)p * d + c] *= rl;
+        __syncthreads();
+        for (int q = threadIdx.x; q < p * d; q += blockDim.x) {
+            const int i = q / d, c = q % d;
+            w.Y[(size_t)i * d + c] -= A[(size_t)p * K + i] * w.Y[(size_t)p * d + c];
+        }
+        __syncthreads();
+    }
     // atoms with a vanishing solution count as unused too
     for (int j = threadIdx.x; j < K; j += blockDim.x) {
         double s = 0.0;
@@ -204,8 +243,18 @@ hipError_t launch_mod_update(const float *X, int64_t N, int d, int K, const int3
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((N + 3) / 4, (int64_t)ncu * 8));
-    hipLaunchKernelGGL(mod_accum_kernel, dim3((unsigned)grid), dim3(256), 0, st, X, N, d, K, idx, coef, count, k, w);
+    const int R = mod_rows(K, d), nblk = (K + R - 1) / R;
+    const int nslices = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * 2 / nblk + 1, (N + 63) / 64));
+    const size_t smem = sizeof(double) * ((size_t)R * K + (size_t)R * d);
+    static bool attr = false;
+    if (!attr) {
+        if ((e = hipFuncSetAttribute((const void *)mod_accum_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(sizeof(double) * kModLdsDoubles))) != hipSuccess)
+            return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(mod_accum_kernel, dim3((unsigned)(nblk * nslices)), dim3(1024), smem, st, X, N, d, K, idx,
+                       coef, count, k, nslices, w);
     hipLaunchKernelGGL(mod_solve_kernel, dim3(1), dim3(1024), 0, st, d, K, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int nb = 0;

@@ -510,67 +510,91 @@ constexpr int kRefitMax = 32;
 struct RefitScratch {
     int sel[kRefitMax];
     double z[kRefitMax];
-    double Gd[kRefitMax * kRefitMax];
+    double Gd[kRefitMax * (kRefitMax + 1) / 2];   // lower triangle, row-packed
+    float Di[kRefitMax * 64];                     // the selected atoms, row t at 64 t
+    float xs[64];
 };
 
-// G_II gamma = D_I^T x with G_II and D_I^T x summed in FP64, solved by
-// Cholesky (lane 0); writes gamma, the explicit residual and count = n.
+__device__ __forceinline__ int tri(int t, int u) { return t * (t + 1) / 2 + u; }   // u <= t
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// G_II gamma = D_I^T x with G_II and D_I^T x summed in FP64 and solved by a
+// Cholesky factorisation, all lane-parallel in LDS: the selected atoms are
+// staged once, the n (n + 1) / 2 Gram entries are spread over the lanes, and
+// each factorisation / substitution step updates its trailing entries in
+// parallel.  Writes gamma, the explicit residual and count = n.
 __device__ __forceinline__ void refit_one(const DictDev &dict, const OmpParams &p, int64_t sig, int n,
                                           RefitScratch &ws, int lane) {
     const int d = dict.d, k = p.k;
     const float *__restrict__ D = dict.D;
     const float *__restrict__ x = p.X + sig * d;
     if (lane < n) ws.sel[lane] = p.idx[sig * k + lane];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int q = lane; q < n * n; q += 64) {
-        const int t = q / n, u = q - t * n;
-        const float *a = D + (size_t)ws.sel[t] * d;
-        const float *b = D + (size_t)ws.sel[u] * d;
+    if (lane < d) ws.xs[lane] = x[lane];
+    wave_lds_sync();
+    for (int q = lane; q < n * d; q += 64) {
+        const int t = q / d, i = q - t * d;
+        ws.Di[t * 64 + i] = D[(size_t)ws.sel[t] * d + i];
+    }
+    wave_lds_sync();
+    for (int q = lane; q < n * (n + 1) / 2; q += 64) {
+        int t = (int)((sqrtf(8.f * (float)q + 1.f) - 1.f) * 0.5f);
+        while (tri(t + 1, 0) <= q) ++t;   // guard the float root
+        while (tri(t, 0) > q) --t;
+        const int u = q - tri(t, 0);
         double s = 0.0;
-        for (int i = 0; i < d; ++i) s += (double)a[i] * (double)b[i];
-        ws.Gd[t * kRefitMax + u] = s;
+        for (int i = 0; i < d; ++i) s += (double)ws.Di[t * 64 + i] * (double)ws.Di[u * 64 + i];
+        ws.Gd[q] = s;
     }
     if (lane < n) {
-        const float *a = D + (size_t)ws.sel[lane] * d;
         double s = 0.0;
-        for (int i = 0; i < d; ++i) s += (double)a[i] * (double)x[i];
+        for (int i = 0; i < d; ++i) s += (double)ws.Di[lane * 64 + i] * (double)ws.xs[i];
         ws.z[lane] = s;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane == 0) {
-        double *Gd = ws.Gd, *z = ws.z;
-        for (int t = 0; t < n; ++t) {   // G = R R^T, R lower, in place
-            for (int u = 0; u <= t; ++u) {
-                double s = Gd[t * kRefitMax + u];
-                for (int v = 0; v < u; ++v) s -= Gd[t * kRefitMax + v] * Gd[u * kRefitMax + v];
-                Gd[t * kRefitMax + u] = (u == t) ? sqrt(fmax(s, 1e-300)) : s / Gd[u * kRefitMax + u];
-            }
+    wave_lds_sync();
+    double *Gd = ws.Gd, *z = ws.z;
+    for (int j = 0; j < n; ++j) {   // right-looking: G = R R^T, R lower, in place
+        const double v = Gd[tri(j, j)];
+        const double rjj = sqrt(fmax(v, 1e-300));
+        wave_lds_sync();
+        if (lane == 0) Gd[tri(j, j)] = rjj;
+        if (j + 1 + lane < n) Gd[tri(j + 1 + lane, j)] /= rjj;
+        wave_lds_sync();
+        const int m = n - j - 1;
+        for (int q = lane; q < m * (m + 1) / 2; q += 64) {
+            int a = (int)((sqrtf(8.f * (float)q + 1.f) - 1.f) * 0.5f);
+            while (tri(a + 1, 0) <= q) ++a;
+            while (tri(a, 0) > q) --a;
+            const int i = j + 1 + a, c = j + 1 + (q - tri(a, 0));
+            Gd[tri(i, c)] -= Gd[tri(i, j)] * Gd[tri(c, j)];
         }
-        for (int t = 0; t < n; ++t) {   // R y = z
-            double s = z[t];
-            for (int u = 0; u < t; ++u) s -= Gd[t * kRefitMax + u] * z[u];
-            z[t] = s / Gd[t * kRefitMax + t];
-        }
-        for (int t = n - 1; t >= 0; --t) {   // R^T gamma = y
-            double s = z[t];
-            for (int u = t + 1; u < n; ++u) s -= Gd[u * kRefitMax + t] * z[u];
-            z[t] = s / Gd[t * kRefitMax + t];
-        }
+        wave_lds_sync();
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int t = 0; t < n; ++t) {   // R y = z
+        const double yt = z[t] / Gd[tri(t, t)];
+        wave_lds_sync();
+        if (lane == 0) z[t] = yt;
+        if (t + 1 + lane < n) z[t + 1 + lane] -= Gd[tri(t + 1 + lane, t)] * yt;
+        wave_lds_sync();
+    }
+    for (int t = n - 1; t >= 0; --t) {   // R^T gamma = y
+        const double gt = z[t] / Gd[tri(t, t)];
+        wave_lds_sync();
+        if (lane == 0) z[t] = gt;
+        if (lane < t) z[lane] -= Gd[tri(t, lane)] * gt;
+        wave_lds_sync();
+    }
     double r = 0.0;
     if (lane < d) {
-        r = (double)x[lane];
-        for (int t = 0; t < n; ++t) r -= ws.z[t] * (double)D[(size_t)ws.sel[t] * d + lane];
+        r = (double)ws.xs[lane];
+        for (int t = 0; t < n; ++t) r -= z[t] * (double)ws.Di[t * 64 + lane];
     }
     const double r2 = wave_sum_d(lane < d ? r * r : 0.0);
-    if (lane < n) p.coef[sig * k + lane] = (float)ws.z[lane];
+    if (lane < n) p.coef[sig * k + lane] = (float)z[lane];
     if (lane == 0) {
         p.count[sig] = n;
         if (p.resid) p.resid[sig] = (float)sqrt(r2);

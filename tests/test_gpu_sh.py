@@ -62,6 +62,35 @@ def test_per_signal_directions(K, k):
     assert np.abs(rgb - exp).max() <= ATOL
 
 
+@pytest.mark.parametrize("k", [4, 12])
+def test_vector_and_entrywise_code_rows_agree(k):
+    """Code rows read as 16-byte vectors (aligned rows, k = 4 or 12) and entry
+    by entry (the same rows 4 bytes off alignment) give the same radiance (up
+    to the compiler's FMA contraction of the direction norm), across a
+    grid-stride loop of several items per thread."""
+    rng = I.rng_for(90 + k)
+    K, N = 512, 300_000
+    D = I.random_dictionary(rng, K)
+    idx, cf, cnt = random_codes(rng, N, K, k)
+    dirs = I.unit_directions(rng, N)
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    ti, tc = torch.from_numpy(idx).to(DEV), torch.from_numpy(cf).to(DEV)
+    tn, td = torch.from_numpy(cnt).to(DEV), torch.from_numpy(dirs).to(DEV)
+    a = sc.sh_eval_sparse(h, ti, tc, tn, td, sc.DIRS_PER_SIGNAL).cpu().numpy()
+    bi = torch.empty(N * k + 1, dtype=torch.int32, device=DEV)
+    bc = torch.empty(N * k + 1, dtype=torch.float32, device=DEV)
+    ui, uc = bi[1:].view(N, k), bc[1:].view(N, k)
+    ui.copy_(ti)
+    uc.copy_(tc)
+    assert ui.data_ptr() % 16 and uc.data_ptr() % 16
+    b = sc.sh_eval_sparse(h, ui, uc, tn, td, sc.DIRS_PER_SIGNAL).cpu().numpy()
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-6)
+    sel = rng.choice(N, 2000, replace=False)
+    exp = oracle.radiance(D, idx[sel], cf[sel], cnt[sel], dirs[sel], shared_dirs=False)
+    assert np.abs(a[sel] - exp).max() <= ATOL
+    h.destroy()
+
+
 @pytest.mark.parametrize("d", [9, 24])
 def test_lower_sh_degrees(d):
     rng = I.rng_for(90 + d)
