@@ -101,7 +101,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the encoder shards by rows with no exchange, "
-              "and multi-GPU runs are not part of this build", file=sys.stderr)
+              "and this encoder is measured on a single GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -238,8 +238,8 @@ hipError_t launch_mod_update(const float *X, int64_t N, int d, int K, const int3
                              hipStream_t st) {
     ModWork w = mod_layout(ws, d, K);
     hipError_t e;
-    if ((e = hipMemsetAsync(w.XAt, 0, sizeof(double) * (size_t)K * d, st)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(w.AAt, 0, sizeof(double) * (size_t)K * K, st)) != hipSuccess) return e;
+    if ((e = launch_zero_words(w.XAt, 2 * (int64_t)K * d, st)) != hipSuccess) return e;
+    if ((e = launch_zero_words(w.AAt, 2 * (int64_t)K * K, st)) != hipSuccess) return e;
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);

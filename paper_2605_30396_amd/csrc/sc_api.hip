@@ -505,7 +505,7 @@ int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, i
     const int kmax = sc::pick_kmax(k);
     const int rel = (flags & SC_EPS_RELATIVE) ? 1 : 0;
     const int refit = (flags & SC_NO_FP64_REFIT) ? 0 : 1;
-    SC_HIP(hipMemsetAsync(miss_count, 0, sizeof(int32_t), st), "sc_omp_encode_learned");
+    SC_HIP(sc::launch_zero_words(miss_count, 1, st), "sc_omp_encode_learned");
     SC_HIP(sc::launch_proposer_topk(p->dev(), X, N, n_cand, cand, nullptr, st), "sc_omp_encode_learned (proposer)");
     const int kcap = h->restricted_cap > 0 ? std::min(h->restricted_cap, k) : k;
     sc::RompParams rp{X, N, k, eps, rel, refit, kKappaMax, kcap, cand, n_cand, idx, coef, count, resid, miss_rows,
@@ -529,7 +529,7 @@ int sc_omp_encode_restricted(sc_dict h, const float *X, int64_t N, int k, float 
     if (flags & ~(SC_EPS_RELATIVE | SC_NO_FP64_REFIT)) return SC_EINVAL;
     if (!miss_count) return SC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    SC_HIP(hipMemsetAsync(miss_count, 0, sizeof(int32_t), st), "sc_omp_encode_restricted");
+    SC_HIP(sc::launch_zero_words(miss_count, 1, st), "sc_omp_encode_restricted");
     if (N == 0) return SC_OK;
     if (!X || !cand || !idx || !coef || !count || !miss_rows) return SC_EINVAL;
     const int kcap = h->restricted_cap > 0 ? std::min(h->restricted_cap, k) : k;
@@ -778,7 +778,7 @@ int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, i
     const int64_t ld1 = f32 ? d : 64;
     const char *fn = "sc_proposer_train_step";
     using sc::GemmArgs;
-    SC_HIP(hipMemsetAsync(loss, 0, sizeof(float), st), fn);
+    SC_HIP(sc::launch_zero_words(loss, 1, st), fn);
     SC_HIP(sc::launch_train_prep(X, rows, B, d, xh, f32, st), fn);
     // forward
     GemmArgs g1{(int)B, H, 48, xh, 64, 1, Wb1, 1, ld1, sc::EPI_GELU, H, b1, nullptr, nullptr, H, h1, H, a1};

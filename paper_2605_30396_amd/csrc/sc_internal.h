@@ -130,6 +130,9 @@ struct GemmArgs {
 
 // Number of K-slices of a STORE-epilogue product with few output tiles
 // (weight gradients); 1 = no split.
+// Zero nwords 32-bit words at p (a kernel, not hipMemsetAsync).
+hipError_t launch_zero_words(void *p, int64_t nwords, hipStream_t st);
+
 int gemm_splits(int M, int N, int K);
 hipError_t launch_gemm(const GemmArgs &g, bool f32, hipStream_t st);
 hipError_t launch_train_prep(const float *X, const int32_t *rows, int64_t B, int d, void *xh, bool f32,
