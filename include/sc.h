@@ -287,7 +287,10 @@ int sc_screen_topk(sc_dict h, const float *X, int64_t N, int n_cand, int32_t *ca
  * explicit-residual acceptance; accepted codes are written to idx/coef/
  * count/resid, the other signals' indices are appended to miss_rows
  * (device int32[N]) and counted in *miss_count (device int32, zeroed by the
- * call).  Same limits as sc_omp_encode_learned.
+ * call).  The order of miss_rows varies from call to call (rows are appended
+ * as workgroups finish); the set does not.  The restricted pursuit takes at
+ * most the handle's restricted-step cap (SC_TUNE_RESTRICTED_CAP, 0 = k)
+ * steps.  Same limits as sc_omp_encode_learned.
  */
 int sc_omp_encode_restricted(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, const int32_t *cand,
                              int n_cand, int32_t *idx, float *coef, int32_t *count, float *resid, int32_t *miss_rows,
