@@ -18,9 +18,11 @@
 //   3. each writer lane appends its logits >= theta to a private slot list,
 //      as keys that order like the logit with the atom index in the low bits
 //      (unique keys, lower index wins a tie) -- about n_cand + 5 survivors;
-//   4. eight lanes per signal (eight signals per wave at once) delete the
-//      smallest survivor until n_cand remain, mark the chosen atoms in a bit
-//      mask and write them in increasing atom index.
+//   4. eight lanes per signal (eight signals per wave at once) pack the
+//      survivors into a dense list and keep each survivor that fewer than
+//      n_cand others exceed (when some signal of the wave has more than 64
+//      survivors: delete the smallest until n_cand remain), mark the chosen
+//      atoms in a bit mask and write them in increasing atom index.
 // A signal whose slot lists overflow (many logits tied at the threshold) or
 // whose input is not finite gets candidate list {-1, ...}: the encoder then
 // sends it straight to the full-OMP fallback.  Keys keep the top 32 - IB bits
@@ -39,6 +41,7 @@ constexpr int kPH = 256;       // hidden width
 constexpr int kXS = 72;        // LDS row stride (bf16) of the input tile
 constexpr int kHS = 264;       // LDS row stride (bf16) of a hidden tile
 constexpr int kNG = 64;        // group maxima per signal
+constexpr int kRankPer = 8;    // survivors ranked per selection lane (rank path: <= 64 per signal)
 
 constexpr int kXBytes = kPT * kXS * 2;        //  9216
 constexpr int kHBytes = kPT * kHS * 2;        // 33792
@@ -321,15 +324,16 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         {
             const int g = lane & 7, s = 8 * wave + (lane >> 3);
             uint32_t key[WPL * kSlots];
-            int over = 0, have = 0;
+            int over = 0, have = 0, cw[WPL];
             uint32_t lim[WPL];   // wave-wide bound on the filled slots of writer block w
 #pragma unroll
             for (int w = 0; w < WPL; ++w) {
                 const int wrq = g + 8 * w;
                 const int c = wcnt[s * NWR + wrq];
+                cw[w] = min(c, kSlots);
                 over |= c > kSlots;
-                have += min(c, kSlots);
-                lim[w] = wave_max_u32((uint32_t)min(c, kSlots));
+                have += cw[w];
+                lim[w] = wave_max_u32((uint32_t)cw[w]);
 #pragma unroll
                 for (int e = 0; e < kSlots; ++e)
                     key[w * kSlots + e] = e < c ? slots[(s * NWR + wrq) * kSlots + e] : 0u;
@@ -337,39 +341,92 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             over = grp8_sum(over);
             have = grp8_sum(have);
             const bool skip = s >= nt_sig || bad[s] || over || have < n_cand;
-            // delete the smallest survivor until n_cand remain (keys are
-            // unique; an empty slot holds 0, i.e. ~0 after the shift below)
-            int excess = skip ? 0 : have - n_cand;
-            while (__ballot(excess > 0) != 0) {
-                uint32_t mn = 0xFFFFFFFFu;
+            uint32_t *mw = mask + s * MW;
+            for (int w = g; w < MW; w += 8) mw[w] = 0u;
+            const int hv = skip ? 0 : have;
+            const uint32_t maxS = wave_max_u32((uint32_t)hv);
+            if (maxS <= 8 * kRankPer) {
+                // Rank selection: the signal's survivors are packed into a dense
+                // list (its own slot region), and a survivor is kept iff fewer
+                // than n_cand survivors exceed it (keys are unique).  The work is
+                // survivors^2 / 8 compares per lane, whatever the excess.
+                int m = 0;
+#pragma unroll
+                for (int w = 0; w < WPL; ++w) m += cw[w];
+                int base = m;   // exclusive prefix of m over the 8 lanes of the group
+#pragma unroll
+                for (int sh = 1; sh < 8; sh <<= 1) {
+                    const int t = __shfl_up(base, sh, 8);
+                    if (g >= sh) base += t;
+                }
+                base -= m;
+                uint32_t *lst = slots + (s * NWR) * kSlots;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();   // every lane holds its keys before the region is rewritten
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                int j = base;
 #pragma unroll
                 for (int w = 0; w < WPL; ++w)
 #pragma unroll
                     for (int e = 0; e < kSlots; ++e)
-                        if ((uint32_t)e < lim[w]) mn = min(mn, key[w * kSlots + e] - 1u);
-                mn = grp8_min(mn);
-                if (excess > 0) {
+                        if ((uint32_t)e < lim[w] && e < cw[w]) lst[j++] = key[w * kSlots + e];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // one survivor per pass (entries g, g + 8, ...): count the list
+                // entries above it, four at a time
+#pragma unroll
+                for (int i = 0; i < kRankPer; ++i) {
+                    if ((uint32_t)(8 * i) < maxS) {
+                        const int q = g + 8 * i;
+                        const uint32_t v = q < hv ? lst[q] : 0u;
+                        int r = 0;
+                        for (uint32_t u = 0; u < maxS; u += 4) {
+                            const uint4 x = *reinterpret_cast<const uint4 *>(lst + u);
+                            r += ((int)u < hv && x.x > v) ? 1 : 0;
+                            r += ((int)u + 1 < hv && x.y > v) ? 1 : 0;
+                            r += ((int)u + 2 < hv && x.z > v) ? 1 : 0;
+                            r += ((int)u + 3 < hv && x.w > v) ? 1 : 0;
+                        }
+                        if (q < hv && r < n_cand) {
+                            const uint32_t at = IMASK - (v & IMASK);
+                            atomicOr(&mw[at >> 5], 1u << (at & 31));
+                        }
+                    }
+                }
+            } else {
+                // many survivors somewhere in the wave: delete the smallest
+                // until n_cand remain (an empty slot holds 0, i.e. ~0 after the
+                // shift below)
+                int excess = skip ? 0 : have - n_cand;
+                while (__ballot(excess > 0) != 0) {
+                    uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
                     for (int w = 0; w < WPL; ++w)
 #pragma unroll
                         for (int e = 0; e < kSlots; ++e)
-                            if ((uint32_t)e < lim[w] && key[w * kSlots + e] - 1u == mn) key[w * kSlots + e] = 0u;
-                    --excess;
-                }
-            }
-            // mark the chosen atoms, then list them in increasing index
-            uint32_t *mw = mask + s * MW;
-            for (int w = g; w < MW; w += 8) mw[w] = 0u;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (!skip) {
+                            if ((uint32_t)e < lim[w]) mn = min(mn, key[w * kSlots + e] - 1u);
+                    mn = grp8_min(mn);
+                    if (excess > 0) {
 #pragma unroll
-                for (int e = 0; e < WPL * kSlots; ++e)
-                    if (key[e] != 0u) {
-                        const uint32_t i = IMASK - (key[e] & IMASK);
-                        atomicOr(&mw[i >> 5], 1u << (i & 31));
+                        for (int w = 0; w < WPL; ++w)
+#pragma unroll
+                            for (int e = 0; e < kSlots; ++e)
+                                if ((uint32_t)e < lim[w] && key[w * kSlots + e] - 1u == mn) key[w * kSlots + e] = 0u;
+                        --excess;
                     }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (!skip) {
+#pragma unroll
+                    for (int e = 0; e < WPL * kSlots; ++e)
+                        if (key[e] != 0u) {
+                            const uint32_t i = IMASK - (key[e] & IMASK);
+                            atomicOr(&mw[i >> 5], 1u << (i & 31));
+                        }
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
