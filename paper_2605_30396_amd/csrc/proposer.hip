@@ -42,6 +42,7 @@ constexpr int kXS = 72;        // LDS row stride (bf16) of the input tile
 constexpr int kHS = 264;       // LDS row stride (bf16) of a hidden tile
 constexpr int kNG = 64;        // group maxima per signal
 constexpr int kRankPer = 8;    // survivors ranked per selection lane (rank path: <= 64 per signal)
+constexpr int kThetaLowBit = 11;   // lowest key bit the threshold search resolves
 
 constexpr int kXBytes = kPT * kXS * 2;        //  9216
 constexpr int kHBytes = kPT * kHS * 2;        // 33792
@@ -288,7 +289,11 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             const int hb = lo == hi ? -1 : 31 - __clz(lo ^ hi);
             uint32_t tau = hb < 0 ? lo : (hb == 31 ? 0u : hi & ~((2u << hb) - 1u));
             const int hbw = (int)wave_max_u32((uint32_t)(hb + 1)) - 1;
-            for (int bit = hbw; bit >= 0; --bit) {   // largest tau with >= n_cand maxima at or above it
+            // largest tau with >= n_cand maxima at or above it, resolved down to
+            // bit kThetaLowBit (the low mantissa bits left at zero only lower
+            // tau by < 2^-12 relative: a still-safe bound, at most a few more
+            // survivors, and fewer search steps)
+            for (int bit = hbw; bit >= kThetaLowBit; --bit) {
                 const uint32_t t2 = tau | (1u << bit);
                 int c = 0;
 #pragma unroll
