@@ -122,3 +122,32 @@ def test_learned_encode_composition():
     # accepted restricted codes use only candidate atoms
     for i in np.nonzero(~fb)[0]:
         assert set(few["idx"][i, : few["count"][i]]) <= set(few["cand"][i])
+
+
+def test_learned_encode_step_cap():
+    """A restricted-step cap c keeps exactly the restricted codes that reach
+    eps within c atoms (they equal the uncapped restricted codes of those
+    signals); every other signal is the full OMP code, and cap = k changes
+    nothing."""
+    rng = I.rng_for(43)
+    D = I.random_dictionary(rng, 64)
+    X2, _, _ = I.sparse_signals(rng, D, 300, 2, 1e-3)
+    X4, _, _ = I.sparse_signals(rng, D, 300, 4, 1e-3)
+    X = np.concatenate([X2, X4])
+    P = I.mlp_init(rng, 45, 32, 64)
+    k, eps, nc = 8, 1e-2, 32
+    full = oracle.omp(D, X, k, eps)
+    base = oracle.learned_encode(D, X, P, k, eps, n_cand=nc)
+    same = oracle.learned_encode(D, X, P, k, eps, n_cand=nc, cap=k)
+    for key in ("idx", "count", "fallback"):
+        np.testing.assert_array_equal(base[key], same[key])
+    capped = oracle.learned_encode(D, X, P, k, eps, n_cand=nc, cap=3)
+    acc = ~capped["fallback"]
+    assert acc.any() and capped["fallback"].any()
+    assert np.all(capped["count"][acc] <= 3) and np.all(capped["resid"][acc] <= eps)
+    np.testing.assert_array_equal(capped["idx"][acc], base["idx"][acc])          # same restricted path
+    np.testing.assert_array_equal(capped["idx"][~acc], full["idx"][~acc])
+    # a signal accepted uncapped with more than 3 atoms is a miss under the cap
+    long_ok = (~base["fallback"]) & (base["count"] > 3)
+    assert long_ok.any() and np.all(capped["fallback"][long_ok])
+    assert capped["idx"].shape == (len(X), k)
