@@ -175,21 +175,17 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
         const bool cand_ok = first >= 0;
         __builtin_amdgcn_wave_barrier();
         // ---- alpha0 over the candidates ----
-        // Lane g takes features 6g .. 6g+5 of every candidate, so the group's
-        // eight lanes read one contiguous 192-byte dictionary row together
-        // (scattered per-lane rows cost one cache-line access per lane); the
-        // partial dots are summed over the group and each candidate's sum is
-        // kept by the lane that owns it in the pursuit.
+        // Lane g takes features 4g .. 4g+3 and 32+2g, 33+2g of every candidate
+        // (one 16-byte and one 8-byte load), so the group's eight lanes read
+        // one contiguous 192-byte dictionary row together (scattered per-lane
+        // rows cost one cache-line access per lane); the partial dots are
+        // summed over the group and each candidate's sum is kept by the lane
+        // that owns it in the pursuit.
 #pragma unroll
         for (int e = 0; e < kRCpl; ++e) gs.cand[g * kRCpl + e] = cid[e];
         __builtin_amdgcn_wave_barrier();
-        float xg[6];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const float2 v = *reinterpret_cast<const float2 *>(gs.x + 6 * g + 2 * q);
-            xg[2 * q] = v.x;
-            xg[2 * q + 1] = v.y;
-        }
+        const float4 xa = *reinterpret_cast<const float4 *>(gs.x + 4 * g);
+        const float2 xb = *reinterpret_cast<const float2 *>(gs.x + 32 + 2 * g);
         vR al;
 #pragma unroll
         for (int e = 0; e < kRCpl; ++e) al[e] = 0.f;
@@ -198,19 +194,19 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
 #pragma unroll
         for (int b = 0; b < 8 * kRCpl / kCB; ++b) {
             if (kCB * b >= nc) break;   // uniform: slots past the list are -1 (NaN below)
-            float2 dv[kCB][3];
+            float4 da[kCB];
+            float2 db[kCB];
 #pragma unroll
             for (int u = 0; u < kCB; ++u) {
                 const int c = gs.cand[kCB * b + u];
-                const float2 *row = reinterpret_cast<const float2 *>(D48 + (size_t)(c < 0 ? 0 : c) * 48 + 6 * g);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) dv[u][q] = row[q];
+                const float *row = D48 + (size_t)(c < 0 ? 0 : c) * 48;
+                da[u] = *reinterpret_cast<const float4 *>(row + 4 * g);
+                db[u] = *reinterpret_cast<const float2 *>(row + 32 + 2 * g);
             }
 #pragma unroll
             for (int u = 0; u < kCB; ++u) {
-                float part = 0.f;
-#pragma unroll
-                for (int q = 0; q < 3; ++q) part = fmaf(dv[u][q].y, xg[2 * q + 1], fmaf(dv[u][q].x, xg[2 * q], part));
+                float part = fmaf(da[u].x, xa.x, fmaf(da[u].y, xa.y, fmaf(da[u].z, xa.z, da[u].w * xa.w)));
+                part = fmaf(db[u].x, xb.x, fmaf(db[u].y, xb.y, part));
                 part = grp_sum(part);
                 const int cq = kCB * b + u;   // owned by lane cq / kRCpl, entry cq % kRCpl
                 if (g == cq / kRCpl) al[cq % kRCpl] = part;
