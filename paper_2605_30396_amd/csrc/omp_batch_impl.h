@@ -25,9 +25,26 @@ __global__ __launch_bounds__(kOmpThreads) void omp_batch_kernel(DictDev dict, Om
         asm volatile("" : "+v"(tid));
         omp_tile<E, KMAX, kTileS, MODE == A0_MFMA_BF16X3, RCQ>(dict, p, MODE, s0, nt, smem_raw, tid, tally);
     }
-    if (p.stats && (threadIdx.x & 63) == 0 && tally.sig) {
-        atomicAdd(p.stats + 0, tally.sig);
-        atomicAdd(p.stats + 1, tally.atoms);
+    // counters: one pair of atomics per workgroup (device-wide atomics on one
+    // address serialise, and every wave ends at about the same time)
+    __shared__ unsigned long long red[kOmpWaves][2];
+    if (p.stats) {
+        if ((threadIdx.x & 63) == 0) {
+            red[threadIdx.x >> 6][0] = tally.sig;
+            red[threadIdx.x >> 6][1] = tally.atoms;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long sg = 0, at = 0;
+            for (int w = 0; w < kOmpWaves; ++w) {
+                sg += red[w][0];
+                at += red[w][1];
+            }
+            if (sg) {
+                atomicAdd(p.stats + 0, sg);
+                atomicAdd(p.stats + 1, at);
+            }
+        }
     }
 }
 

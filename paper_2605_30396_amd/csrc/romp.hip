@@ -20,7 +20,7 @@ namespace sc {
 
 constexpr int kRCpl = 4;           // candidates per lane (n_cand <= 32)
 constexpr int kRThreads = 256;
-constexpr int kMissQ = 128;        // fallback rows queued per wave before one atomic reserves their slots
+constexpr int kMissQ = 256;        // fallback rows queued per wave before one atomic reserves their slots
 
 template <int KMAX>
 struct GroupScratch {
@@ -421,7 +421,8 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
         __builtin_amdgcn_wave_barrier();
     }
     flush_misses();
-    if (p.stats) {   // one atomic per counter and wave
+    if (p.stats) {   // one atomic per counter and workgroup
+        __shared__ unsigned int red[kRThreads / 64][4];
         const unsigned long long v[4] = {n_sig, n_atoms, n_refit, n_miss};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -429,7 +430,13 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
             t += __shfl_xor(t, 8);
             t += __shfl_xor(t, 16);
             t += __shfl_xor(t, 32);
-            if (lane == 0 && t) atomicAdd(p.stats + c, (unsigned long long)t);
+            if (lane == 0) red[wave][c] = t;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            unsigned long long t = 0;
+            for (int w = 0; w < kRThreads / 64; ++w) t += red[w][tid];
+            if (t) atomicAdd(p.stats + tid, t);
         }
     }
 }

@@ -155,7 +155,7 @@ __global__ void train_prep_kernel(const float *__restrict__ X, const int32_t *__
 // the row's q-th support atom and the membership test reads it by lane index.
 // Waves stride over the B K / 64 chunks with a bounded grid, so the loss takes
 // one atomic per block.
-constexpr int kBceBlocks = 1024;
+constexpr int kBceBlocks = 128;   // few blocks: one loss atomic each on a single address
 template <bool F32>
 __global__ __launch_bounds__(256) void bce_grad_kernel(const float *__restrict__ Z, int64_t B, int K,
                                                        const int32_t *__restrict__ rows,
