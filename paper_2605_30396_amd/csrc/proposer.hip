@@ -457,29 +457,40 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     }
 }
 
-// FP32 master parameters -> BF16 MFMA copies (W1 padded to 64 inputs).
+// FP32 master parameters -> BF16 MFMA copies (W1 padded to 64 inputs), plus
+// transposed BF16 copies of W2 and W3 for the backward products of training
+// (their reduction index is then contiguous).
 __global__ void proposer_pack_kernel(const float *__restrict__ params, int d, int H, int K, uint16_t *__restrict__ W1b,
-                                     uint16_t *__restrict__ W2b, uint16_t *__restrict__ W3b) {
+                                     uint16_t *__restrict__ W2b, uint16_t *__restrict__ W3b,
+                                     uint16_t *__restrict__ W2bT, uint16_t *__restrict__ W3bT) {
     const int64_t n1 = (int64_t)H * 64, n2 = (int64_t)H * H, n3 = (int64_t)K * H;
     const float *W1 = params;
     const float *W2 = W1 + (size_t)H * d + H;
     const float *W3 = W2 + (size_t)H * H + H;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n1 + n2 + n3;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n1 + 2 * (n2 + n3);
          t += (int64_t)gridDim.x * blockDim.x) {
         if (t < n1) {
             int i = (int)(t / 64), f = (int)(t % 64);
             W1b[t] = bf16_bits(f < d ? W1[(size_t)i * d + f] : 0.f);
         } else if (t < n1 + n2) {
             W2b[t - n1] = bf16_bits(W2[t - n1]);
-        } else {
+        } else if (t < n1 + n2 + n3) {
             W3b[t - n1 - n2] = bf16_bits(W3[t - n1 - n2]);
+        } else if (t < n1 + 2 * n2 + n3) {
+            const int64_t q = t - n1 - n2 - n3;   // W2bT[j][i] = W2[i][j]
+            const int64_t j = q / H, i = q - j * H;
+            if (W2bT) W2bT[q] = bf16_bits(W2[i * H + j]);
+        } else {
+            const int64_t q = t - n1 - 2 * n2 - n3;   // W3bT[j][i] = W3[i][j], i < K, j < H
+            const int64_t j = q / K, i = q - j * K;
+            if (W3bT) W3bT[q] = bf16_bits(W3[i * H + j]);
         }
     }
 }
 
 hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16_t *W1b, uint16_t *W2b,
-                                uint16_t *W3b, hipStream_t st) {
-    proposer_pack_kernel<<<1024, 256, 0, st>>>(params, d, H, K, W1b, W2b, W3b);
+                                uint16_t *W3b, uint16_t *W2bT, uint16_t *W3bT, hipStream_t st) {
+    proposer_pack_kernel<<<1024, 256, 0, st>>>(params, d, H, K, W1b, W2b, W3b, W2bT, W3bT);
     return hipGetLastError();
 }
 

@@ -391,6 +391,8 @@ static void free_proposer(sc_proposer p) {
     hipFree(p->W1b);
     hipFree(p->W2b);
     hipFree(p->W3b);
+    hipFree(p->W2bT);
+    hipFree(p->W3bT);
     delete p;
 }
 
@@ -409,7 +411,9 @@ int sc_proposer_create(int d, int H, int K, sc_proposer *out) {
               hipMalloc(&p->v, pb) == hipSuccess && hipMalloc(&p->grads, pb) == hipSuccess &&
               hipMalloc(&p->W1b, sizeof(uint16_t) * (size_t)H * 64) == hipSuccess &&
               hipMalloc(&p->W2b, sizeof(uint16_t) * (size_t)H * H) == hipSuccess &&
-              hipMalloc(&p->W3b, sizeof(uint16_t) * (size_t)K * H) == hipSuccess;
+              hipMalloc(&p->W3b, sizeof(uint16_t) * (size_t)K * H) == hipSuccess &&
+              hipMalloc(&p->W2bT, sizeof(uint16_t) * (size_t)H * H) == hipSuccess &&
+              hipMalloc(&p->W3bT, sizeof(uint16_t) * (size_t)K * H) == hipSuccess;
     if (!ok ||
         hipMemset(p->params, 0, pb) != hipSuccess || hipMemset(p->m, 0, pb) != hipSuccess ||
         hipMemset(p->v, 0, pb) != hipSuccess || hipMemset(p->grads, 0, pb) != hipSuccess) {
@@ -445,7 +449,7 @@ int sc_proposer_set_params(sc_proposer p, const float *params, void *stream) {
     SC_HIP(hipMemsetAsync(p->m, 0, pb, st), "sc_proposer_set_params");
     SC_HIP(hipMemsetAsync(p->v, 0, pb, st), "sc_proposer_set_params");
     p->step = 0;
-    SC_HIP(sc::launch_proposer_pack(p->params, p->d, p->H, p->K, p->W1b, p->W2b, p->W3b, st),
+    SC_HIP(sc::launch_proposer_pack(p->params, p->d, p->H, p->K, p->W1b, p->W2b, p->W3b, p->W2bT, p->W3bT, st),
            "sc_proposer_set_params");
     return SC_OK;
 }
@@ -792,12 +796,19 @@ int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, i
     GemmArgs gw3{K, H, (int)B, dz, 1, K, h2, H, 1, sc::EPI_STORE, H, nullptr, nullptr, gW3, H, nullptr, 0, nullptr, part};
     SC_HIP(sc::launch_gemm(gw3, f32, st), fn);
     SC_HIP(sc::launch_colsum(dz, B, K, K, gb3, f32, st), fn);
-    GemmArgs gd2{(int)B, H, K, dz, K, 1, Wb3, H, 1, sc::EPI_DGELU, H, nullptr, a2, nullptr, H, da2, H, nullptr};
+    // B(k, j) = W3[k][j]: the transposed BF16 copy makes k contiguous (vector loads)
+    GemmArgs gd2 = f32 ? GemmArgs{(int)B, H, K, dz, K, 1, Wb3, H, 1, sc::EPI_DGELU, H, nullptr, a2, nullptr, H, da2, H,
+                                  nullptr}
+                       : GemmArgs{(int)B, H, K, dz, K, 1, p->W3bT, 1, K, sc::EPI_DGELU, H, nullptr, a2, nullptr, H,
+                                  da2, H, nullptr};
     SC_HIP(sc::launch_gemm(gd2, f32, st), fn);
     GemmArgs gw2{H, H, (int)B, da2, 1, H, h1, H, 1, sc::EPI_STORE, H, nullptr, nullptr, gW2, H, nullptr, 0, nullptr, part};
     SC_HIP(sc::launch_gemm(gw2, f32, st), fn);
     SC_HIP(sc::launch_colsum(da2, B, H, H, gb2, f32, st), fn);
-    GemmArgs gd1{(int)B, H, H, da2, H, 1, Wb2, H, 1, sc::EPI_DGELU, H, nullptr, a1, nullptr, H, da1, H, nullptr};
+    GemmArgs gd1 = f32 ? GemmArgs{(int)B, H, H, da2, H, 1, Wb2, H, 1, sc::EPI_DGELU, H, nullptr, a1, nullptr, H, da1, H,
+                                  nullptr}
+                       : GemmArgs{(int)B, H, H, da2, H, 1, p->W2bT, 1, H, sc::EPI_DGELU, H, nullptr, a1, nullptr, H,
+                                  da1, H, nullptr};
     SC_HIP(sc::launch_gemm(gd1, f32, st), fn);
     GemmArgs gw1{H, 64, (int)B, da1, 1, H, xh, 64, 1, sc::EPI_STORE, d, nullptr, nullptr, gW1, d, nullptr, 0, nullptr, part};
     SC_HIP(sc::launch_gemm(gw1, f32, st), fn);
@@ -812,7 +823,7 @@ int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, i
         const float lr_t = (float)(lr * sqrt(bc2) / bc1);
         const float eps_hat = (float)(adam_eps * sqrt(bc2));
         SC_HIP(sc::launch_adam(p->params, p->m, p->v, p->grads, p->nparams, lr_t, beta1, beta2, eps_hat, st), fn);
-        SC_HIP(sc::launch_proposer_pack(p->params, d, H, K, p->W1b, p->W2b, p->W3b, st), fn);
+        SC_HIP(sc::launch_proposer_pack(p->params, d, H, K, p->W1b, p->W2b, p->W3b, p->W2bT, p->W3bT, st), fn);
     }
     return SC_OK;
 }

@@ -103,7 +103,7 @@ hipError_t launch_omp_multi(const sc_scene *scenes, const int *order, int n, int
 hipError_t launch_omp_restricted(const DictDev &dict, const float *D48, const RompParams &p, int kmax,
                                  hipStream_t st);
 hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16_t *W1b, uint16_t *W2b,
-                                uint16_t *W3b, hipStream_t st);
+                                uint16_t *W3b, uint16_t *W2bT, uint16_t *W3bT, hipStream_t st);
 hipError_t launch_screen_topk(const uint16_t *Dbf, int d, int K, const float *X, int64_t N, int n_cand,
                               int32_t *cand, hipStream_t st);
 hipError_t launch_proposer_topk(const PropDev &P, const float *X, int64_t N, int n_cand, int32_t *cand,
@@ -185,6 +185,7 @@ struct sc_proposer_s {
     float *v = nullptr;          // Adam second moment
     float *grads = nullptr;      // gradient buffer (same layout)
     uint16_t *W1b = nullptr, *W2b = nullptr, *W3b = nullptr;
+    uint16_t *W2bT = nullptr, *W3bT = nullptr;   // transposed copies for the backward products
     int64_t step = 0;
     sc::PropDev dev() const {
         const float *b1 = params + (size_t)H * d;
