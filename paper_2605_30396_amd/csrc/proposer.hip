@@ -328,20 +328,15 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         // ---- exact top-n_cand: 8 lanes per signal, 8 signals per wave ----
         {
             const int g = lane & 7, s = 8 * wave + (lane >> 3);
-            uint32_t key[WPL * kSlots];
             int over = 0, have = 0, cw[WPL];
             uint32_t lim[WPL];   // wave-wide bound on the filled slots of writer block w
 #pragma unroll
             for (int w = 0; w < WPL; ++w) {
-                const int wrq = g + 8 * w;
-                const int c = wcnt[s * NWR + wrq];
+                const int c = wcnt[s * NWR + g + 8 * w];
                 cw[w] = min(c, kSlots);
                 over |= c > kSlots;
                 have += cw[w];
                 lim[w] = wave_max_u32((uint32_t)cw[w]);
-#pragma unroll
-                for (int e = 0; e < kSlots; ++e)
-                    key[w * kSlots + e] = e < c ? slots[(s * NWR + wrq) * kSlots + e] : 0u;
             }
             over = grp8_sum(over);
             have = grp8_sum(have);
@@ -366,18 +361,26 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 }
                 base -= m;
                 uint32_t *lst = slots + (s * NWR) * kSlots;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();   // every lane holds its keys before the region is rewritten
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // one writer block per phase: every lane reads its block's keys,
+                // then writes them packed; all destinations lie below 64, under
+                // the second block's sources (writers 8..15 start at 8 kSlots)
                 int j = base;
 #pragma unroll
-                for (int w = 0; w < WPL; ++w)
+                for (int w = 0; w < WPL; ++w) {
+                    uint32_t kk[kSlots];
+                    const uint32_t *src = slots + (s * NWR + g + 8 * w) * kSlots;
+#pragma unroll
+                    for (int e = 0; e < kSlots; ++e) kk[e] = ((uint32_t)e < lim[w] && e < cw[w]) ? src[e] : 0u;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
                     for (int e = 0; e < kSlots; ++e)
-                        if ((uint32_t)e < lim[w] && e < cw[w]) lst[j++] = key[w * kSlots + e];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        if ((uint32_t)e < lim[w] && e < cw[w]) lst[j++] = kk[e];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
                 // one survivor per pass (entries g, g + 8, ...): count the list
                 // entries above it, four at a time
 #pragma unroll
@@ -403,6 +406,12 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 // many survivors somewhere in the wave: delete the smallest
                 // until n_cand remain (an empty slot holds 0, i.e. ~0 after the
                 // shift below)
+                uint32_t key[WPL * kSlots];
+#pragma unroll
+                for (int w = 0; w < WPL; ++w)
+#pragma unroll
+                    for (int e = 0; e < kSlots; ++e)
+                        key[w * kSlots + e] = e < cw[w] ? slots[(s * NWR + g + 8 * w) * kSlots + e] : 0u;
                 int excess = skip ? 0 : have - n_cand;
                 while (__ballot(excess > 0) != 0) {
                     uint32_t mn = 0xFFFFFFFFu;
