@@ -84,7 +84,8 @@ static hipError_t launch_batch_mode(const DictDev &dict, const OmpParams &p, int
                                     hipStream_t st) {
 #define SC_CASE(EE, KK)                                                                  \
     if (dict.E == EE && kmax == KK) {                                                    \
-        if (EE <= 8 && row_cache > 0) return launch_batch_t<EE, KK, MODE, 4>(dict, p, st); \
+        if constexpr (EE <= 8)                                                           \
+            if (row_cache > 0) return launch_batch_t<EE, KK, MODE, 4>(dict, p, st);      \
         return launch_batch_t<EE, KK, MODE, 0>(dict, p, st);                             \
     }
     SC_CASE(1, 4) SC_CASE(1, 8) SC_CASE(1, 12) SC_CASE(1, 16) SC_CASE(1, 24) SC_CASE(1, 32)

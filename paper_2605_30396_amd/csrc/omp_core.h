@@ -21,9 +21,10 @@
 // triangular solves run lane-parallel with one v_readlane per step.
 //
 // Selection key: the bits of |alpha_j| with the low 10 mantissa bits replaced
-// by (1023 - j), so one unsigned wave maximum gives the atom, and entries
-// whose magnitudes agree to 2^-13 relative resolve to the lowest index.
-// Selected and padding atoms have their magnitude bits masked off.
+// by (1023 - j) and bit 31 set while the atom is selectable, so one unsigned
+// wave maximum gives the atom, and entries whose magnitudes agree to 2^-13
+// relative resolve to the lowest index.  Selected and padding atoms have
+// bit 31 clear.
 //
 // A support whose Cholesky condition estimate (max L_ii / min L_ii)^2 exceeds
 // kappa_max leaves count = -(2 + n) and the FP32 coefficients; a separate
@@ -40,6 +41,7 @@ constexpr int kOmpThreads = 64 * kOmpWaves;
 constexpr int kXhs = 72;                              // LDS row stride (BF16) of the split signal tile
 constexpr uint32_t kKeyIdx = 1023u;                   // atom index bits of a selection key
 constexpr uint32_t kKeyMag = 0x7FFFFFFFu & ~kKeyIdx;  // magnitude bits of a selection key
+constexpr uint32_t kKeyLive = 0x80000000u;            // set while the atom may still be selected
 
 // Row stride (floats) of the alpha0 tile in LDS: 4 floats past Kp, so the
 // 16 rows an MFMA result writes at once start 16 bytes apart and spread over
@@ -250,17 +252,21 @@ __device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)
 // recomputed in FP32 from the signal, so the coefficients, the tracked
 // residual and the stop test carry no BF16 error.
 // RCQ: the Gram rows of the atoms of the first RCQ steps are kept in
-// registers (RCQ * E VGPRs); later rows are re-read whenever alpha is formed.
+// registers (RCQ * E VGPRs).  The row of the newest atom is fetched as soon
+// as the atom is chosen and held for the next step; older rows are re-read
+// kRowBatch at a time whenever alpha is formed.
 template <int E, int KMAX, bool kSplit, int T, int RCQ>
 __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams &p, int64_t sig, int s,
                                             const float *__restrict__ Xt, const float *__restrict__ A0, int lane,
                                             OmpTally &tally) {
     constexpr int Kp = 64 * E;
     constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
+    constexpr int kRowBatch = 3;
     const int d = dict.d, K = dict.K, k = p.k;
     const float *__restrict__ G = dict.G;
     const float *__restrict__ Dg = dict.D;
     const float xv = lane < d ? Xt[lane * T + s] : 0.f;
+    const int dl = lane < d ? lane : d - 1;   // in-bounds row offset for the idle lanes
     int32_t *oidx = p.idx + sig * k;
     float *ocoef = p.coef + sig * k;
     if (ballot(lane < d && !isfinite(xv)) != 0) {   // status -1, padded slots
@@ -281,15 +287,16 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     const float band = 1e-5f * xx;     // FP32 uncertainty of the tracked ||r||^2
     const float brk = 1e-6f * xnorm;   // residual orthogonal to every atom
 
+    // Key bit 31 marks an atom still selectable: any such key beats every
+    // retired or padding atom, whatever their magnitude bits.
     float a0[E];
-    uint32_t msk[E], kid[E];
+    uint32_t kid[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int j = lane * E + e;
         const bool real = j < K;
         a0[e] = real ? A0[s * a0_stride(Kp) + j] : 0.f;
-        msk[e] = real ? kKeyMag : 0u;
-        kid[e] = kKeyIdx - (uint32_t)j;
+        kid[e] = (real ? kKeyLive : 0u) | (kKeyIdx - (uint32_t)j);
     }
     float Lrow[KMAX], Lcol[KMAX];   // lane t: L[t][u] (u < t) and L[u][t] (u > t)
 #pragma unroll
@@ -300,33 +307,45 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     float cval = 0.f, linv = 1.f, gam = 0.f;   // lane t: c_t, 1 / L_tt, gamma_t
     int selv = 0;                               // lane t: atom of step t
     float rc[RC > 0 ? RC : 1][E];   // G rows of the atoms of steps t < RC
+    float nrow[E];                  // G row of the newest atom (step >= RC)
+#pragma unroll
+    for (int e = 0; e < E; ++e) nrow[e] = 0.f;
     float rr = xx, lmax = 0.f, lmin = 3.4e38f, rr_expl = 0.f;
-    int n = 0, n_gam = -1;   // gamma is current for n_gam atoms
+    int n = 0, n_gam = 0;   // gamma is current for n_gam atoms
     bool active = xx > 0.f, expl_done = false;
 
-    // gamma = L^-T c for the first nn atoms
+    // gamma = L^-T c for the first nn atoms.  Lane t's accumulator stops
+    // changing once step t is passed (column t of L is zero above the
+    // diagonal), so every lane forms its own gamma_t at the end.
     auto back_sub = [&](int nn) {
         float acc = 0.f;
 #pragma unroll
         for (int t = KMAX - 1; t >= 0; --t) {
             if (t < nn) {
                 const float gt = readlane_f((cval - acc) * linv, t);
-                gam = lane == t ? gt : gam;
                 acc = fmaf(Lcol[t], gt, acc);
             }
         }
+        gam = (cval - acc) * linv;
         n_gam = nn;
     };
     // ||x - D_I gamma||^2 with the current gamma (lane i < d holds x_i)
     auto resid2 = [&](int nn) {
         float r = xv;
         nn = __builtin_amdgcn_readfirstlane(nn);
-        asm volatile("" : "+s"(nn));
-#pragma unroll 2
-        for (int t = 0; t < nn; ++t) {
-            const int jt = readlane_i(selv, t);
-            const float gt = readlane_f(gam, t);
-            if (lane < d) r = fmaf(-Dg[(size_t)jt * d + lane], gt, r);
+#pragma unroll
+        for (int t0 = 0; t0 < KMAX; t0 += 4) {
+            if (t0 < nn) {
+                float dv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int jt = readlane_i(selv, t0 + q);
+                    dv[q] = Dg[(size_t)jt * d + dl];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (t0 + q < nn) r = fmaf(-dv[q], readlane_f(gam, t0 + q), r);
+            }
         }
         return wave_sum(lane < d ? r * r : 0.f);
     };
@@ -358,7 +377,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             }
         }
         // ---- correlations of the residual and the selection ----
-        if (n_gam != it) back_sub(it);
+        if (__builtin_amdgcn_readfirstlane(n_gam) != it) back_sub(it);
         float al[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) al[e] = a0[e];
@@ -368,50 +387,61 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 #pragma unroll
             for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, rc[t][e], al[e]);
         }
-        // rows past the cache: a real loop keeps at most two in flight (the
-        // trip count is hidden from the optimiser, which would otherwise
-        // unroll it fully and issue every row load at once)
-        int nrow = it;
-        asm volatile("" : "+s"(nrow));
-#pragma unroll 2
-        for (int t = RC; t < nrow; ++t) {
-            const int jt = readlane_i(selv, t);
-            const float gt = readlane_f(gam, t);
-            float gr[E];
-            load_row<E>(G + (size_t)jt * Kp + lane * E, gr);
+        // rows RC .. it-2 from L2, kRowBatch loads in flight; row it-1 is nrow
 #pragma unroll
-            for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[e], al[e]);
+        for (int t0 = RC; t0 < it - 1; t0 += kRowBatch) {
+            float gr[kRowBatch][E];
+#pragma unroll
+            for (int q = 0; q < kRowBatch; ++q)
+                if (t0 + q < it - 1) load_row<E>(G + (size_t)readlane_i(selv, t0 + q) * Kp + lane * E, gr[q]);
+#pragma unroll
+            for (int q = 0; q < kRowBatch; ++q) {
+                if (t0 + q < it - 1) {
+                    const float gt = readlane_f(gam, t0 + q);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[q][e], al[e]);
+                }
+            }
+        }
+        if (it - 1 >= RC) {
+            const float gt = readlane_f(gam, it - 1);
+#pragma unroll
+            for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, nrow[e], al[e]);
         }
         uint32_t best = 0u;
 #pragma unroll
-        for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & msk[e]) | kid[e]);
+        for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
         const uint32_t kb = wave_max_u32(best);
         if (!(__uint_as_float(kb & kKeyMag) > brk)) {
             active = false;
             continue;
         }
-        const int j = (int)(kKeyIdx - (kb & kKeyIdx));
-        if (it < RC) load_row<E>(G + (size_t)j * Kp + lane * E, rc[it < RC ? it : 0]);
+        const uint32_t kbi = kb & kKeyIdx;
+        const int j = (int)(kKeyIdx - kbi);
+        if (it < RC)
+            load_row<E>(G + (size_t)j * Kp + lane * E, rc[it < RC ? it : 0]);
+        else
+            load_row<E>(G + (size_t)j * Kp + lane * E, nrow);
         // ---- new row of the Cholesky factor: L w = G[I, j] ----
-        float g = 0.f;
-        if (lane < it) g = G[(size_t)selv * Kp + j];
+        const float g = G[(size_t)selv * Kp + j];   // lanes >= it read an unused entry of row 0
         const float gjj = G[(size_t)j * Kp + j];
-        float acc = 0.f, wsq = 0.f, wc = 0.f, wv = 0.f;
+        float acc = 0.f, wsq = 0.f, wc = 0.f;
 #pragma unroll
         for (int t = 0; t < it; ++t) {
             const float wt = readlane_f((g - acc) * linv, t);
             acc = fmaf(Lrow[t], wt, acc);
             wsq = fmaf(wt, wt, wsq);
             wc = fmaf(wt, readlane_f(cval, t), wc);
-            wv = lane == t ? wt : wv;
             Lrow[t] = lane == it ? wt : Lrow[t];
         }
+        // lane t < it holds w_t (its accumulator is final once step t is passed)
+        const float wv = lane < it ? (g - acc) * linv : 0.f;
         const float l2 = gjj - wsq;
         if (!(l2 > 1e-9f * gjj)) {   // numerically dependent on the selected atoms
             active = false;
             continue;
         }
-        const float ell = sqrtf(l2);
+        const float ell = __builtin_amdgcn_sqrtf(l2);
         const float inv = __builtin_amdgcn_rcpf(ell);
         float zj;
         if constexpr (kSplit)
@@ -419,24 +449,21 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         else
             zj = A0[s * a0_stride(Kp) + j];
         const float cn = (zj - wc) * inv;
-        rr = fmaf(-cn, cn, rr);
+        rr = readfirstlane_f(fmaf(-cn, cn, rr));
         lmax = fmaxf(lmax, ell);
         lmin = fminf(lmin, ell);
         Lcol[it] = wv;
-        if (lane == it) {
-            cval = cn;
-            linv = inv;
-            selv = j;
-        }
+        cval = lane == it ? cn : cval;
+        linv = lane == it ? inv : linv;
+        selv = lane == it ? j : selv;
         // retire atom j from the selection
-        const int jl = j / E, je = j - jl * E;
 #pragma unroll
-        for (int e = 0; e < E; ++e) msk[e] = (lane == jl && e == je) ? 0u : msk[e];
+        for (int e = 0; e < E; ++e) kid[e] = kid[e] == (kKeyLive | kbi) ? kbi : kid[e];
         n = it + 1;
     }
 
     // ---- coefficients, residual, outputs ----
-    if (n_gam != n) back_sub(n);
+    if (__builtin_amdgcn_readfirstlane(n_gam) != n) back_sub(n);
     bool refit = false;
     if (n > 0 && p.fp64_refit) {
         const float q = lmax / lmin;
@@ -465,7 +492,8 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
     constexpr int Kp = 64 * E;
     float *A0 = reinterpret_cast<float *>(smem);
     float *Xt = A0 + T * a0_stride(Kp);
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the signal loop below is per wave
     __syncthreads();   // the previous tile is done with Xt and A0
     load_tile<T>(p, dict.d, s0, nt, Xt, tid);
     __syncthreads();

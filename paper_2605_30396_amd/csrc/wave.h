@@ -22,6 +22,12 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
 
 __device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+// Lane 0's value, known to the compiler as wave-uniform (callers pass values
+// that are equal on every lane, so branches on them need no exec masking).
+__device__ __forceinline__ float readfirstlane_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror
 #define SC_DPP_QP1032 0xB1
 #define SC_DPP_QP2301 0x4E
