@@ -261,7 +261,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
                                             OmpTally &tally) {
     constexpr int Kp = 64 * E;
     constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
-    constexpr int kRowBatch = 3;
+    constexpr int kRowBatch = KMAX >= 16 ? 2 : 3;   // 2 keeps the k = 16 class within 128 VGPRs
     const int d = dict.d, K = dict.K, k = p.k;
     const float *__restrict__ G = dict.G;
     const float *__restrict__ Dg = dict.D;
@@ -387,9 +387,13 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 #pragma unroll
             for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, rc[t][e], al[e]);
         }
-        // rows RC .. it-2 from L2, kRowBatch loads in flight; row it-1 is nrow
+        // rows RC .. it-2 from L2: the first kRowBatch with their loads in
+        // flight together, later ones (long supports only) one at a time in
+        // a real loop, whose trip count is kept opaque to the optimiser so
+        // that it does not unroll it and hold every row at once; row it-1 is
+        // nrow
 #pragma unroll
-        for (int t0 = RC; t0 < it - 1; t0 += kRowBatch) {
+        for (int t0 = RC; t0 < (it - 1 < RC + kRowBatch ? it - 1 : RC + kRowBatch); t0 += kRowBatch) {
             float gr[kRowBatch][E];
 #pragma unroll
             for (int q = 0; q < kRowBatch; ++q)
@@ -401,6 +405,16 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 #pragma unroll
                     for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[q][e], al[e]);
                 }
+            }
+        }
+        if (it - 1 > RC + kRowBatch) {
+            const int tend = (it - 1) | (k >> 16);   // k <= 32: the value is it - 1
+            for (int t = RC + kRowBatch; t < tend; ++t) {
+                float gr[E];
+                load_row<E>(G + (size_t)readlane_i(selv, t) * Kp + lane * E, gr);
+                const float gt = readlane_f(gam, t);
+#pragma unroll
+                for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[e], al[e]);
             }
         }
         if (it - 1 >= RC) {
