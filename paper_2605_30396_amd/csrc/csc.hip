@@ -127,6 +127,11 @@ __global__ void csc_fill_kernel(const int32_t *__restrict__ idx, const float *__
     }
 }
 
+// LDS row of an atom: 45 floats padded to 52 (16-byte rows; the odd quotient
+// 13 spreads the rows of random atoms over 16 starting bank groups, where a
+// 48-float row would give 4 and 4-way bank conflicts).
+constexpr int kStride = 52;
+
 // The view-dependent radiance of one CSC column at unit direction (x, y, z).
 template <int NB, bool LDS>
 __device__ __forceinline__ void csc_column_rgb(const float *__restrict__ D, const float *__restrict__ sD, int K,
@@ -134,7 +139,6 @@ __device__ __forceinline__ void csc_column_rgb(const float *__restrict__ D, cons
                                                int64_t c0, int64_t c1, float x, float y, float z, float &r,
                                                float &gr, float &b) {
     constexpr int d = 3 * NB;
-    constexpr int kStride = 48;
     float Y[NB];
     sh_basis<NB>(x, y, z, Y);
     r = gr = b = 0.f;
@@ -167,7 +171,6 @@ __global__ __launch_bounds__(1024) void csc_eval_kernel(const float *__restrict_
                                                         const float *__restrict__ pos, const float *__restrict__ dc,
                                                         float cx, float cy, float cz, float *__restrict__ rgb) {
     constexpr int d = 3 * NB;
-    constexpr int kStride = 48;
     extern __shared__ __align__(16) float sD[];
     if (LDS) {
         for (int q = threadIdx.x; q < K * kStride; q += blockDim.x) {
@@ -244,9 +247,9 @@ static hipError_t launch_csc_eval_t(const DictDev &dict, const int64_t *colptr, 
     const int64_t items = (MODE == 0 && shared) ? N * M : N;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((items + 1023) / 1024, (int64_t)csc_cus()));
     const float cx = cam ? cam[0] : 0.f, cy = cam ? cam[1] : 0.f, cz = cam ? cam[2] : 0.f;
-    constexpr int kLdsAtoms = (128 * 1024) / (48 * 4);
+    constexpr int kLdsAtoms = (128 * 1024) / (kStride * 4);
     if (dict.K <= kLdsAtoms) {
-        const size_t smem = sizeof(float) * (size_t)dict.K * 48;
+        const size_t smem = sizeof(float) * (size_t)dict.K * kStride;
         auto kern = csc_eval_kernel<NB, true, MODE>;
         static bool attr = false;
         if (!attr) {

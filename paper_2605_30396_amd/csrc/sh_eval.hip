@@ -15,7 +15,12 @@
 namespace sc {
 
 constexpr int kShThreads = 1024;
-constexpr int kAtomStride = 48;                 // 45 floats padded to a multiple of 4
+// LDS row of an atom: 45 floats padded to 52, a multiple of 4 (16-byte rows
+// for vector reads) whose quotient 13 is odd, so atom rows start on 16
+// different 4-bank groups of the 64 banks and the random atoms that the
+// lanes of a wave read at once seldom share a bank (a 48-float row has only
+// 4 starting groups: one atom in 16 per group, 4-way conflicts).
+constexpr int kAtomStride = 52;
 constexpr int kShLdsAtoms = (128 * 1024) / (kAtomStride * 4);   // atoms staged in LDS
 
 // KV > 0: code rows of k = 4 KV entries are read as KV 16-byte vectors, and
