@@ -48,11 +48,18 @@ constexpr uint32_t kKeyLive = 0x80000000u;            // set while the atom may 
 // the banks instead of hitting the same ones.
 __host__ __device__ constexpr int a0_stride(int Kp) { return Kp + 4; }
 
+// Row stride (floats) of the feature-major signal tile Xt[64][T]: 4 past T,
+// so a column read (lane = feature) or the tile store spreads over 16 bank
+// groups instead of the 4 that a stride of T = 16 maps to, and rows stay 16
+// bytes aligned for the vector reads of the VALU correlation.
+__host__ __device__ constexpr int xt_stride(int T) { return T + 4; }
+
 // LDS bytes of one workgroup: alpha0 tile [T][a0_stride(Kp)], signal tile
 // [64][T], and for the split-BF16 correlations the two BF16 signal parts
 // [T][kXhs].
 __host__ __device__ constexpr size_t omp_tile_lds(int T, int Kp, bool split) {
-    return sizeof(float) * ((size_t)T * a0_stride(Kp) + 64 * (size_t)T) + (split ? sizeof(uint16_t) * 2 * T * kXhs : 0);
+    return sizeof(float) * ((size_t)T * a0_stride(Kp) + 64 * (size_t)xt_stride(T)) +
+           (split ? sizeof(uint16_t) * 2 * T * kXhs : 0);
 }
 
 struct OmpTally {
@@ -66,18 +73,18 @@ __device__ __forceinline__ void load_tile(const OmpParams &p, int d, int64_t s0,
     if (p.rows) {
         for (int f = tid; f < nt * d; f += kOmpThreads) {
             const int s = f / d, i = f - s * d;
-            Xt[i * T + s] = p.X[(int64_t)p.rows[s0 + s] * d + i];
+            Xt[i * xt_stride(T) + s] = p.X[(int64_t)p.rows[s0 + s] * d + i];
         }
     } else {
         const float *__restrict__ Xtile = p.X + s0 * d;
         for (int f = tid; f < nt * d; f += kOmpThreads) {
             const int s = f / d, i = f - s * d;
-            Xt[i * T + s] = Xtile[f];
+            Xt[i * xt_stride(T) + s] = Xtile[f];
         }
     }
     for (int q = tid; q < 64 * T; q += kOmpThreads) {
         const int i = q / T, s = q - i * T;
-        if (i >= d || s >= nt) Xt[q] = 0.f;
+        if (i >= d || s >= nt) Xt[i * xt_stride(T) + s] = 0.f;
     }
 }
 
@@ -118,7 +125,7 @@ __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d,
                 if constexpr (SG == 1 && SQ % 4 == 0) {
 #pragma unroll
                     for (int q4 = 0; q4 < SQ / 4; ++q4) {
-                        const float4 v = *reinterpret_cast<const float4 *>(Xt + i * T + 4 * q4);
+                        const float4 v = *reinterpret_cast<const float4 *>(Xt + i * xt_stride(T) + 4 * q4);
                         xv[4 * q4] = v.x;
                         xv[4 * q4 + 1] = v.y;
                         xv[4 * q4 + 2] = v.z;
@@ -126,7 +133,7 @@ __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d,
                     }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < SQ; ++q) xv[q] = Xt[i * T + sg + q * SG];
+                    for (int q = 0; q < SQ; ++q) xv[q] = Xt[i * xt_stride(T) + sg + q * SG];
                 }
 #pragma unroll
                 for (int q = 0; q < SQ; ++q)
@@ -181,7 +188,7 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ DT, in
         const int f = k0 + kq;
         float bx[CB];
 #pragma unroll
-        for (int c = 0; c < CB; ++c) bx[c] = Xt[f * T + c * 16 + lr];
+        for (int c = 0; c < CB; ++c) bx[c] = Xt[f * xt_stride(T) + c * 16 + lr];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -265,7 +272,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     const int d = dict.d, K = dict.K, k = p.k;
     const float *__restrict__ G = dict.G;
     const float *__restrict__ Dg = dict.D;
-    const float xv = lane < d ? Xt[lane * T + s] : 0.f;
+    const float xv = lane < d ? Xt[lane * xt_stride(T) + s] : 0.f;
     const int dl = lane < d ? lane : d - 1;   // in-bounds row offset for the idle lanes
     int32_t *oidx = p.idx + sig * k;
     float *ocoef = p.coef + sig * k;
@@ -517,11 +524,11 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
             alpha0_mfma_f32<E, T>(dict.DT, dict.d, Xt, A0, wave, lane);
             done = true;
         } else if (kSplitOK && T == 16 && mode == A0_MFMA_BF16X3) {
-            uint16_t *Xh = reinterpret_cast<uint16_t *>(Xt + 64 * T);
+            uint16_t *Xh = reinterpret_cast<uint16_t *>(Xt + 64 * xt_stride(T));
             uint16_t *Xl = Xh + T * kXhs;
             for (int q = tid; q < T * 64; q += kOmpThreads) {
                 const int s = q >> 6, f = q & 63;
-                const float v = Xt[f * T + s];
+                const float v = Xt[f * xt_stride(T) + s];
                 const uint16_t hi = bf16_bits(v);
                 Xh[s * kXhs + f] = hi;
                 Xl[s * kXhs + f] = bf16_bits(v - bf16_to_f32(hi));

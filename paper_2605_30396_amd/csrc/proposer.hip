@@ -127,6 +127,11 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     constexpr int MW = K / 32;                  // mask words per signal
     constexpr int WPL = NWR / 8;                // writers handled per selection lane
     constexpr int kSlots = VL < 16 ? VL : 16;   // candidate slots per writer lane and signal
+    // per-signal strides of the group maxima and of the slot regions: 4 words
+    // past a multiple of 64, so rows of consecutive signals start on different
+    // bank groups (the lanes of a wave touch up to 32 signals at once)
+    constexpr int kGS = kNG + 4;
+    constexpr int kSS = NWR * kSlots + 4;
                                                 // (= VL for K <= 256: no overflow possible)
     extern __shared__ __align__(16) unsigned char lds[];
     uint16_t *Xh = reinterpret_cast<uint16_t *>(lds);
@@ -138,11 +143,10 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     uint32_t *theta = reinterpret_cast<uint32_t *>(lds);                       // [64] threshold keys
     uint32_t *mask = theta + kPT;                                               // [64][MW]
     uint8_t *wcnt = reinterpret_cast<uint8_t *>(mask + kPT * MW);              // [64][NWR]
-    float *gmax = reinterpret_cast<float *>(wcnt + kPT * NWR);                 // [64][32]
-    uint32_t *slots = reinterpret_cast<uint32_t *>(gmax);                      // [64][NWR][kSlots]
-    static_assert(kPT * 4 + kPT * MW * 4 + kPT * NWR +
-                          (kPT * kNG * 4 > kPT * NWR * kSlots * 4 ? kPT * kNG * 4 : kPT * NWR * kSlots * 4) <=
-                      kPropLds,
+    float *gmax = reinterpret_cast<float *>(wcnt + kPT * NWR);                 // [64][kGS]
+    uint32_t *slots = reinterpret_cast<uint32_t *>(gmax);                      // [64][kSS]: [NWR][kSlots] + pad
+    static_assert(kPT * 4 + kPT * MW * 4 + kPT * NWR + (kGS > kSS ? kGS : kSS) * kPT * 4 <= kPropLds &&
+                      (kPT * 4 + kPT * MW * 4 + kPT * NWR) % 16 == 0,
                   "selection scratch must fit in the tile's LDS");
 
     const int d = P.d;
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 float mx = -__builtin_inff();
 #pragma unroll
                 for (int r = 0; r < GS; ++r) mx = fmaxf(mx, acc[(gg * GS + r) / 16][n][(gg * GS + r) % 16]);
-                gmax[j * kNG + wr * (VL / GS) + gg] = mx;
+                gmax[j * kGS + wr * (VL / GS) + gg] = mx;
             }
         }
         __syncthreads();
@@ -273,8 +277,8 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         {
             const int g = lane & 7, s = 8 * wave + (lane >> 3);
             uint32_t gk[8];
-            const float4 ga = *reinterpret_cast<const float4 *>(gmax + s * kNG + 8 * g);
-            const float4 gb = *reinterpret_cast<const float4 *>(gmax + s * kNG + 8 * g + 4);
+            const float4 ga = *reinterpret_cast<const float4 *>(gmax + s * kGS + 8 * g);
+            const float4 gb = *reinterpret_cast<const float4 *>(gmax + s * kGS + 8 * g + 4);
             gk[0] = order_key(ga.x), gk[1] = order_key(ga.y), gk[2] = order_key(ga.z), gk[3] = order_key(ga.w);
             gk[4] = order_key(gb.x), gk[5] = order_key(gb.y), gk[6] = order_key(gb.z), gk[7] = order_key(gb.w);
             uint32_t lo = gk[0], hi = gk[0];
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         for (int n = 0; n < NPW; ++n) {
             const int j = 32 * (n0 + n) + lr;
             const uint32_t thk = theta[j];
-            uint32_t *myslots = slots + (j * NWR + wr) * kSlots;
+            uint32_t *myslots = slots + j * kSS + wr * kSlots;
             int cnt = 0;
 #pragma unroll
             for (int q = 0; q < MPW; ++q)
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                     if (g >= sh) base += t;
                 }
                 base -= m;
-                uint32_t *lst = slots + (s * NWR) * kSlots;
+                uint32_t *lst = slots + s * kSS;
                 // one writer block per phase: every lane reads its block's keys,
                 // then writes them packed; all destinations lie below 64, under
                 // the second block's sources (writers 8..15 start at 8 kSlots)
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
                 for (int w = 0; w < WPL; ++w) {
                     uint32_t kk[kSlots];
-                    const uint32_t *src = slots + (s * NWR + g + 8 * w) * kSlots;
+                    const uint32_t *src = slots + s * kSS + (g + 8 * w) * kSlots;
 #pragma unroll
                     for (int e = 0; e < kSlots; ++e) kk[e] = ((uint32_t)e < lim[w] && e < cw[w]) ? src[e] : 0u;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -411,7 +415,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 for (int w = 0; w < WPL; ++w)
 #pragma unroll
                     for (int e = 0; e < kSlots; ++e)
-                        key[w * kSlots + e] = e < cw[w] ? slots[(s * NWR + g + 8 * w) * kSlots + e] : 0u;
+                        key[w * kSlots + e] = e < cw[w] ? slots[s * kSS + (g + 8 * w) * kSlots + e] : 0u;
                 int excess = skip ? 0 : have - n_cand;
                 while (__ballot(excess > 0) != 0) {
                     uint32_t mn = 0xFFFFFFFFu;
