@@ -60,7 +60,9 @@ __global__ void dict_layout_kernel(const float *__restrict__ Dc, int d, int K, i
 }
 
 // G[j][l] = <a_j, a_l>, summed in FP64 and rounded once; columns l >= K are 0.
-__global__ void gram_kernel(const float *__restrict__ Dc, int d, int K, int Kp, float *__restrict__ G) {
+// G64 keeps the FP64 sums (the products of FP32 entries are exact in FP64).
+__global__ void gram_kernel(const float *__restrict__ Dc, int d, int K, int Kp, float *__restrict__ G,
+                            double *__restrict__ G64) {
     int l = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y;
     if (l >= Kp) return;
@@ -71,6 +73,7 @@ __global__ void gram_kernel(const float *__restrict__ Dc, int d, int K, int Kp, 
         double s = 0.0;
         for (int i = 0; i < d; ++i) s += (double)a[i] * (double)b[i];
         g = (float)s;
+        G64[(size_t)j * K + l] = s;
     }
     G[(size_t)j * Kp + l] = g;
 }
@@ -88,9 +91,9 @@ hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *
     return hipGetLastError();
 }
 
-hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, hipStream_t st) {
+hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, double *G64, hipStream_t st) {
     dim3 grid((Kp + 255) / 256, K);
-    gram_kernel<<<grid, 256, 0, st>>>(Dcopy, d, K, Kp, G);
+    gram_kernel<<<grid, 256, 0, st>>>(Dcopy, d, K, Kp, G, G64);
     return hipGetLastError();
 }
 

@@ -573,10 +573,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // G_II gamma = D_I^T x with G_II and D_I^T x summed in FP64 and solved by a
-// Cholesky factorisation, all lane-parallel in LDS: the selected atoms are
-// staged once, the n (n + 1) / 2 Gram entries are spread over the lanes, and
-// each factorisation / substitution step updates its trailing entries in
-// parallel.  Writes gamma, the explicit residual and count = n.
+// Cholesky factorisation, all lane-parallel in LDS: G_II is gathered from the
+// dictionary's FP64 Gram (row t by lanes u <= t), the selected atoms are
+// staged once for D_I^T x and the residual, and each factorisation /
+// substitution step updates its trailing entries in parallel.  Writes gamma,
+// the explicit residual and count = n.
 __device__ __forceinline__ void refit_one(const DictDev &dict, const OmpParams &p, int64_t sig, int n,
                                           RefitScratch &ws, int lane) {
     const int d = dict.d, k = p.k;
@@ -590,14 +591,12 @@ __device__ __forceinline__ void refit_one(const DictDev &dict, const OmpParams &
         ws.Di[t * 64 + i] = D[(size_t)ws.sel[t] * d + i];
     }
     wave_lds_sync();
-    for (int q = lane; q < n * (n + 1) / 2; q += 64) {
-        int t = (int)((sqrtf(8.f * (float)q + 1.f) - 1.f) * 0.5f);
-        while (tri(t + 1, 0) <= q) ++t;   // guard the float root
-        while (tri(t, 0) > q) --t;
-        const int u = q - tri(t, 0);
-        double s = 0.0;
-        for (int i = 0; i < d; ++i) s += (double)ws.Di[t * 64 + i] * (double)ws.Di[u * 64 + i];
-        ws.Gd[q] = s;
+    {
+        const double *__restrict__ G64 = dict.G64;
+        const size_t su = lane < n ? (size_t)ws.sel[lane] : 0;
+#pragma unroll 4
+        for (int t = 0; t < n; ++t)
+            if (lane <= t) ws.Gd[tri(t, lane)] = G64[(size_t)ws.sel[t] * dict.K + su];
     }
     if (lane < n) {
         double s = 0.0;

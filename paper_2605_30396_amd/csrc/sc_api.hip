@@ -52,6 +52,7 @@ void free_dict(sc_dict h) {
     hipFree(h->Dbf);
     hipFree(h->Dlo);
     hipFree(h->D48);
+    hipFree(h->G64);
     hipFree(h->status);
     hipFree(h->stats);
     hipFree(h->ddev);
@@ -95,6 +96,7 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
               hipMalloc(&h->Dbf, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->Dlo, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->D48, sizeof(float) * (size_t)K * 48) == hipSuccess &&
+              hipMalloc(&h->G64, sizeof(double) * (size_t)K * K) == hipSuccess &&
               hipMalloc(&h->status, sizeof(int) * 4) == hipSuccess &&
               hipMalloc(&h->stats, sizeof(unsigned long long) * 4) == hipSuccess;
     if (!ok) {
@@ -121,12 +123,12 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
         return SC_ENORM;
     }
     if ((e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->D48, st)) != hipSuccess ||
-        (e = sc::launch_gram(h->D, d, K, Kp, h->G, st)) != hipSuccess ||
+        (e = sc::launch_gram(h->D, d, K, Kp, h->G, h->G64, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         free_dict(h);
         return set_dev_error("sc_gram_precompute", e);
     }
-    h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->D48};
+    h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->D48, h->G64};
     h->row_cache = E <= 4 ? 4 : 0;
     // device copy of the layout descriptor, read by the multi-scene encoder
     if ((e = hipMalloc(&h->ddev, sizeof(sc::DictDev))) != hipSuccess ||

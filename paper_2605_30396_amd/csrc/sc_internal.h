@@ -34,6 +34,7 @@ struct DictDev {
     const uint16_t *Dbf;  // Kp x 64 BF16 atom-major, features and atoms zero padded
     const uint16_t *Dlo;  // Kp x 64 BF16 residual D - bf16(D) (split-BF16 products)
     const float *D48;     // K x 48 FP32 atom-major, features zero padded (d <= 48)
+    const double *G64;    // K x K Gram, exact products summed in FP64 (not rounded)
 };
 
 // How the correlation tile alpha0 = D^T X is computed by the batch encoder.
@@ -91,7 +92,7 @@ hipError_t launch_dict_check(const float *D, int d, int K, int normalize, float 
                              hipStream_t st);
 hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *DT, uint16_t *Dbf, uint16_t *Dlo,
                                float *D48, hipStream_t st);
-hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, hipStream_t st);
+hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, double *G64, hipStream_t st);
 hipError_t launch_omp_batch(const DictDev &dict, const OmpParams &p, int kmax, int a0mode, int row_cache,
                             hipStream_t st);
 hipError_t launch_omp_batch_valu(const DictDev &dict, const OmpParams &p, int kmax, int row_cache, hipStream_t st);
@@ -169,6 +170,7 @@ struct sc_dict_s {
     uint16_t *Dbf = nullptr;
     uint16_t *Dlo = nullptr;
     float *D48 = nullptr;   // K x 48 FP32, atoms padded to 16-byte rows
+    double *G64 = nullptr;  // K x K FP64 Gram (the FP64 refit's entries)
     int *status = nullptr;
     unsigned long long *stats = nullptr;
     int a0_fp32 = sc::A0_VALU;       // alpha0 stage of the FP32 encoder (tunable)
