@@ -268,7 +268,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
                                             OmpTally &tally) {
     constexpr int Kp = 64 * E;
     constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
-    constexpr int kRowBatch = KMAX >= 16 ? 2 : 3;   // 2 keeps the k = 16 class within 128 VGPRs
+    constexpr int kRowBatch = RCQ > 0 ? 1 : (KMAX >= 16 ? 2 : 3);   // within 128 VGPRs (4 waves per SIMD)
     const int d = dict.d, K = dict.K, k = p.k;
     const float *__restrict__ G = dict.G;
     const float *__restrict__ Dg = dict.D;
