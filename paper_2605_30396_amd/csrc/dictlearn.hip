@@ -94,8 +94,12 @@ __device__ __forceinline__ double block_sum_d(double v, double *red) {
 }
 
 // One workgroup: ridge, Cholesky of A A^T + ridge I, two triangular solves
-// for the d right-hand sides, unused-atom flags.
+// for the d right-hand sides, unused-atom flags.  YL: the right-hand sides
+// are solved in LDS (K d <= kModSolveLds doubles), else in place in w.Y.
+constexpr int kModSolveLds = 12288;   // 96 KB
+template <bool YL>
 __global__ __launch_bounds__(1024) void mod_solve_kernel(int d, int K, ModWork w) {
+    extern __shared__ __align__(16) double sY[];
     __shared__ double red[16];
     __shared__ double diag_sh;
     double *A = w.AAt;
@@ -111,8 +115,11 @@ __global__ __launch_bounds__(1024) void mod_solve_kernel(int d, int K, ModWork w
     for (int j = threadIdx.x; j < K; j += blockDim.x) A[(size_t)j * K + j] += ridge;
     __syncthreads();
     // right-looking Cholesky, A = L L^T in the lower triangle: for each column,
-    // the pivot, the scaled column, then the trailing update spread over the
-    // whole workgroup
+    // the pivot, the scaled column (also kept in LDS), then the trailing lower
+    // triangle updated by 32 x 32 threads (thread rows over i, lanes over
+    // consecutive c, so each row's update is one coalesced run)
+    __shared__ double colj[1024];   // K <= 1024
+    const int tr_i = threadIdx.x >> 5, tr_c = threadIdx.x & 31;
     for (int j = 0; j < K; ++j) {
         if (threadIdx.x == 0) {
             const double v = A[(size_t)j * K + j];
@@ -121,43 +128,54 @@ __global__ __launch_bounds__(1024) void mod_solve_kernel(int d, int K, ModWork w
         }
         __syncthreads();
         const double rl = 1.0 / diag_sh;
-        for (int i = j + 1 + threadIdx.x; i < K; i += blockDim.x) A[(size_t)i * K + j] *= rl;
+        for (int i = j + 1 + threadIdx.x; i < K; i += blockDim.x) {
+            const double v = A[(size_t)i * K + j] * rl;
+            A[(size_t)i * K + j] = v;
+            colj[i] = v;
+        }
         __syncthreads();
-        const int m = K - j - 1;   // trailing block (j+1 .. K-1), lower triangle incl. diagonal
-        for (int64_t q = threadIdx.x; q < (int64_t)m * m; q += blockDim.x) {
-            const int i = j + 1 + (int)(q / m), c = j + 1 + (int)(q % m);
-            if (c <= i) A[(size_t)i * K + c] -= A[(size_t)i * K + j] * A[(size_t)c * K + j];
+        for (int i = j + 1 + tr_i; i < K; i += 32) {
+            const double li = colj[i];
+            double *Ai = A + (size_t)i * K;
+            for (int c = j + 1 + tr_c; c <= i; c += 32) Ai[c] -= li * colj[c];
         }
         __syncthreads();
     }
     // L Z = XAt, then L^T Y = Z, column-oriented: each step finishes one row of
-    // the d right-hand sides and updates the remaining rows in parallel
-    for (int q = threadIdx.x; q < K * d; q += blockDim.x) w.Y[q] = w.XAt[q];
+    // the d right-hand sides (d <= 64: lane = right-hand side, the 16 waves
+    // over rows) and updates the remaining rows in parallel
+    double *Y = YL ? sY : w.Y;
+    for (int q = threadIdx.x; q < K * d; q += blockDim.x) Y[q] = w.XAt[q];
     __syncthreads();
+    const int sc_c = threadIdx.x & 63, sc_r = threadIdx.x >> 6, nrw = blockDim.x >> 6;
     for (int p = 0; p < K; ++p) {
         const double rl = 1.0 / A[(size_t)p * K + p];
-        for (int c = threadIdx.x; c < d; c += blockDim.x) w.Y[(size_t)p * d + c] *= rl;
+        if (threadIdx.x < d) Y[(size_t)p * d + threadIdx.x] *= rl;
         __syncthreads();
-        for (int q = threadIdx.x; q < (K - p - 1) * d; q += blockDim.x) {
-            const int i = p + 1 + q / d, c = q % d;
-            w.Y[(size_t)i * d + c] -= A[(size_t)i * K + p] * w.Y[(size_t)p * d + c];
+        if (sc_c < d) {
+            const double yp = Y[(size_t)p * d + sc_c];
+            for (int i = p + 1 + sc_r; i < K; i += nrw) Y[(size_t)i * d + sc_c] -= A[(size_t)i * K + p] * yp;
         }
         __syncthreads();
     }
     for (int p = K - 1; p >= 0; --p) {
         const double rl = 1.0 / A[(size_t)p * K + p];
-        for (int c = threadIdx.x; c < d; c += blockDim.x) w.Y[(size_t)p * d + c] *= rl;
+        if (threadIdx.x < d) Y[(size_t)p * d + threadIdx.x] *= rl;
         __syncthreads();
-        for (int q = threadIdx.x; q < p * d; q += blockDim.x) {
-            const int i = q / d, c = q % d;
-            w.Y[(size_t)i * d + c] -= A[(size_t)p * K + i] * w.Y[(size_t)p * d + c];
+        if (sc_c < d) {
+            const double yp = Y[(size_t)p * d + sc_c];
+            for (int i = sc_r; i < p; i += nrw) Y[(size_t)i * d + sc_c] -= A[(size_t)p * K + i] * yp;
         }
+        __syncthreads();
+    }
+    if (YL) {
+        for (int q = threadIdx.x; q < K * d; q += blockDim.x) w.Y[q] = sY[q];
         __syncthreads();
     }
     // atoms with a vanishing solution count as unused too
     for (int j = threadIdx.x; j < K; j += blockDim.x) {
         double s = 0.0;
-        for (int c = 0; c < d; ++c) s += w.Y[(size_t)j * d + c] * w.Y[(size_t)j * d + c];
+        for (int c = 0; c < d; ++c) s += Y[(size_t)j * d + c] * Y[(size_t)j * d + c];
         if (!(sqrt(s) > 1e-12)) w.flags[j] = 1;
     }
     __syncthreads();
@@ -255,7 +273,19 @@ hipError_t launch_mod_update(const float *X, int64_t N, int d, int K, const int3
     }
     hipLaunchKernelGGL(mod_accum_kernel, dim3((unsigned)(nblk * nslices)), dim3(1024), smem, st, X, N, d, K, idx,
                        coef, count, k, nslices, w);
-    hipLaunchKernelGGL(mod_solve_kernel, dim3(1), dim3(1024), 0, st, d, K, w);
+    if (K * d <= kModSolveLds) {
+        static bool sattr = false;
+        if (!sattr) {
+            if ((e = hipFuncSetAttribute((const void *)mod_solve_kernel<true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(sizeof(double) * kModSolveLds))) != hipSuccess)
+                return e;
+            sattr = true;
+        }
+        hipLaunchKernelGGL(mod_solve_kernel<true>, dim3(1), dim3(1024), sizeof(double) * (size_t)K * d, st, d, K, w);
+    } else {
+        hipLaunchKernelGGL(mod_solve_kernel<false>, dim3(1), dim3(1024), 0, st, d, K, w);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int nb = 0;
     if ((e = hipMemcpyAsync(&nb, w.nbad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
