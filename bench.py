@@ -157,8 +157,12 @@ def main():
         tuned = saved["encoder"]
         h.set_tuning(sc.TUNE_FP32_CORRELATION, tuned["corr"])
         h.set_tuning(sc.TUNE_ROW_CACHE, tuned["row_cache"])
+        if "row_cache_bf16" in tuned:
+            h.set_tuning(sc.TUNE_ROW_CACHE_BF16, tuned["row_cache_bf16"])
     else:
         tuned = autotune.tune_dictionary(h, Xg, k, eps, use_cache=False)
+        tuned["row_cache_bf16"] = autotune.tune_dictionary(h, Xg, k, eps, sc.PREC_BF16,
+                                                           use_cache=False)["row_cache_bf16"]
     log(f"encoder tuning {tuned}")
 
     # ---- train the proposer (untimed) ----

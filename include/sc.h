@@ -146,6 +146,9 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
  *     registers by the encoder: 0 (default for K > 256: every row re-read
  *     from cache memory when the correlations are formed) or 4 (applies to
  *     K <= 512).
+ *   SC_TUNE_ROW_CACHE_BF16  the same choice for the split-BF16 form
+ *     (SC_PREC_BF16), whose encoder holds more registers, so its best value
+ *     can differ.
  *   SC_TUNE_RESTRICTED_CAP  at most this many restricted-OMP steps in
  *     sc_omp_encode_learned / _restricted (0 = k, default).  A signal whose
  *     candidate code is still above eps after the cap goes to the full-OMP
@@ -155,6 +158,7 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
 #define SC_TUNE_FP32_CORRELATION 1
 #define SC_TUNE_ROW_CACHE 2
 #define SC_TUNE_RESTRICTED_CAP 3
+#define SC_TUNE_ROW_CACHE_BF16 4
 #define SC_CORR_VALU 0
 #define SC_CORR_MFMA 1
 int sc_dict_set_tuning(sc_dict h, int key, int value);

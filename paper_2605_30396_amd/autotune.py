@@ -71,7 +71,11 @@ def _time(fn, reps=3):
 
 def tune_dictionary(h: sc.Dictionary, X, k, eps=0.0, flags=0, sample=262144, use_cache=True):
     """Pick the fastest correlation stage and row cache of sc_omp_encode for
-    this handle on X[:sample]; returns {"corr", "row_cache", "ms"}."""
+    this handle on X[:sample]; returns {"corr", "row_cache", "ms"}.  With
+    PREC_BF16 in flags only the split-BF16 form's row cache is tuned and
+    {"row_cache_bf16", "ms"} is returned."""
+    if flags & sc.PREC_BF16:
+        return _tune_bf16(h, X, k, eps, flags, sample, use_cache)
     key = (f"{_device_name(X.device)}|dict|K={h.K}|d={h.d}|k={k}|eps={float(eps):.3g}|flags={int(flags)}"
            f"|n={min(len(X), sample)}")
     if use_cache:
@@ -96,6 +100,32 @@ def tune_dictionary(h: sc.Dictionary, X, k, eps=0.0, flags=0, sample=262144, use
                 best = {"corr": corr, "row_cache": rc, "ms": ms}
     h.set_tuning(sc.TUNE_FP32_CORRELATION, best["corr"])
     h.set_tuning(sc.TUNE_ROW_CACHE, best["row_cache"])
+    if use_cache:
+        _store(key, best)
+    return best
+
+
+def _tune_bf16(h, X, k, eps, flags, sample, use_cache):
+    key = (f"{_device_name(X.device)}|dict-bf16|K={h.K}|d={h.d}|k={k}|eps={float(eps):.3g}|flags={int(flags)}"
+           f"|n={min(len(X), sample)}")
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            h.set_tuning(sc.TUNE_ROW_CACHE_BF16, hit["row_cache_bf16"])
+            return hit
+    Xs = X[:sample]
+    n = Xs.shape[0]
+    out = (torch.empty((n, k), dtype=torch.int32, device=X.device),
+           torch.empty((n, k), dtype=torch.float32, device=X.device),
+           torch.empty((n,), dtype=torch.int32, device=X.device),
+           torch.empty((n,), dtype=torch.float32, device=X.device))
+    best = None
+    for rc in (0, 4):
+        h.set_tuning(sc.TUNE_ROW_CACHE_BF16, rc)
+        ms = _time(lambda: sc.omp_encode(h, Xs, k, eps, flags, out=out))
+        if best is None or ms < best["ms"]:
+            best = {"row_cache_bf16": rc, "ms": ms}
+    h.set_tuning(sc.TUNE_ROW_CACHE_BF16, best["row_cache_bf16"])
     if use_cache:
         _store(key, best)
     return best

@@ -54,12 +54,19 @@ __host__ __device__ constexpr int a0_stride(int Kp) { return Kp + 4; }
 // bytes aligned for the vector reads of the VALU correlation.
 __host__ __device__ constexpr int xt_stride(int T) { return T + 4; }
 
+// The two BF16 signal parts [T][kXhs] of the split-BF16 correlations live
+// inside the alpha0 tile when it is large enough: they are read only before
+// the tile is written.
+__host__ __device__ constexpr bool split_in_a0(int T, int Kp) {
+    return 2 * T * kXhs * (int)sizeof(uint16_t) <= T * a0_stride(Kp) * (int)sizeof(float);
+}
+
 // LDS bytes of one workgroup: alpha0 tile [T][a0_stride(Kp)], signal tile
-// [64][T], and for the split-BF16 correlations the two BF16 signal parts
-// [T][kXhs].
+// [64][xt_stride(T)], and for the split-BF16 correlations the two BF16
+// signal parts when they do not fit inside the alpha0 tile.
 __host__ __device__ constexpr size_t omp_tile_lds(int T, int Kp, bool split) {
     return sizeof(float) * ((size_t)T * a0_stride(Kp) + 64 * (size_t)xt_stride(T)) +
-           (split ? sizeof(uint16_t) * 2 * T * kXhs : 0);
+           (split && !split_in_a0(T, Kp) ? sizeof(uint16_t) * 2 * T * kXhs : 0);
 }
 
 struct OmpTally {
@@ -227,6 +234,7 @@ __device__ __forceinline__ void alpha0_mfma_bf16x3(const uint16_t *__restrict__ 
             acc[b] = mfma16(ah, bh, acc[b]);
         }
     }
+    __syncthreads();   // every wave has read Xh and Xl, which may share the alpha0 tile
 #pragma unroll
     for (int b = 0; b < NB; ++b)
         *reinterpret_cast<floatx4 *>(A0 + lr * a0_stride(Kp) + (wave + kOmpWaves * b) * 16 + 4 * kq) = acc[b];
@@ -524,7 +532,8 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
             alpha0_mfma_f32<E, T>(dict.DT, dict.d, Xt, A0, wave, lane);
             done = true;
         } else if (kSplitOK && T == 16 && mode == A0_MFMA_BF16X3) {
-            uint16_t *Xh = reinterpret_cast<uint16_t *>(Xt + 64 * xt_stride(T));
+            uint16_t *Xh = split_in_a0(T, Kp) ? reinterpret_cast<uint16_t *>(A0)
+                                              : reinterpret_cast<uint16_t *>(Xt + 64 * xt_stride(T));
             uint16_t *Xl = Xh + T * kXhs;
             for (int q = tid; q < T * 64; q += kOmpThreads) {
                 const int s = q >> 6, f = q & 63;

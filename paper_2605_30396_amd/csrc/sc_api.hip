@@ -59,6 +59,11 @@ void free_dict(sc_dict h) {
     delete h;
 }
 
+// Row-cache setting of the encoder that `flags` selects (FP32 or split BF16).
+int row_cache_for(const sc_dict_s *h, int flags) {
+    return (flags & SC_PREC_BF16) ? h->row_cache_bf16 : h->row_cache;
+}
+
 }  // namespace
 
 extern "C" {
@@ -130,6 +135,7 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
     }
     h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->D48, h->G64};
     h->row_cache = E <= 4 ? 4 : 0;
+    h->row_cache_bf16 = h->row_cache;
     // device copy of the layout descriptor, read by the multi-scene encoder
     if ((e = hipMalloc(&h->ddev, sizeof(sc::DictDev))) != hipSuccess ||
         (e = hipMemcpy(h->ddev, &h->dev, sizeof(sc::DictDev), hipMemcpyHostToDevice)) != hipSuccess) {
@@ -177,7 +183,7 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
                     (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, idx, coef, count, resid, h->stats};
     hipStream_t st = (hipStream_t)stream;
     const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
-    hipError_t e = sc::launch_omp_batch(h->dev, p, kmax, a0, h->row_cache, st);
+    hipError_t e = sc::launch_omp_batch(h->dev, p, kmax, a0, row_cache_for(h, flags), st);
     if (e == hipErrorInvalidValue) {
         snprintf(g_last_error, sizeof(g_last_error), "no compiled encoder for K=%d (Kp=%d) with k=%d", K,
                  h->dev.Kp, k);
@@ -194,9 +200,9 @@ int sc_dict_set_tuning(sc_dict h, int key, int value) {
         h->a0_fp32 = value == SC_CORR_VALU ? sc::A0_VALU : sc::A0_MFMA_F32;
         return SC_OK;
     }
-    if (key == SC_TUNE_ROW_CACHE) {
+    if (key == SC_TUNE_ROW_CACHE || key == SC_TUNE_ROW_CACHE_BF16) {
         if (value != 0 && value != 4) return SC_EINVAL;
-        h->row_cache = value;
+        (key == SC_TUNE_ROW_CACHE ? h->row_cache : h->row_cache_bf16) = value;
         return SC_OK;
     }
     if (key == SC_TUNE_RESTRICTED_CAP) {
@@ -213,8 +219,8 @@ int sc_dict_get_tuning(sc_dict h, int key, int *value) {
         *value = h->a0_fp32 == sc::A0_VALU ? SC_CORR_VALU : SC_CORR_MFMA;
         return SC_OK;
     }
-    if (key == SC_TUNE_ROW_CACHE) {
-        *value = h->row_cache;
+    if (key == SC_TUNE_ROW_CACHE || key == SC_TUNE_ROW_CACHE_BF16) {
+        *value = key == SC_TUNE_ROW_CACHE ? h->row_cache : h->row_cache_bf16;
         return SC_OK;
     }
     if (key == SC_TUNE_RESTRICTED_CAP) {
@@ -520,7 +526,7 @@ int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, i
     SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, sc::pick_kmax(kcap), st), "sc_omp_encode_learned (restricted)");
     sc::OmpParams fp{X, N, miss_rows, miss_count, k, eps, rel, refit, kKappaMax, idx, coef, count, resid, h->stats};
     const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
-    SC_HIP(sc::launch_omp_batch(h->dev, fp, kmax, a0, h->row_cache, st), "sc_omp_encode_learned (fallback)");
+    SC_HIP(sc::launch_omp_batch(h->dev, fp, kmax, a0, row_cache_for(h, flags), st), "sc_omp_encode_learned (fallback)");
     return SC_OK;
 }
 
@@ -557,7 +563,7 @@ int sc_omp_encode_rows(sc_dict h, const float *X, const int32_t *rows, const int
     sc::OmpParams p{X, max_rows, rows, nrows, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0,
                     (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, idx, coef, count, resid, h->stats};
     const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
-    hipError_t e = sc::launch_omp_batch(h->dev, p, sc::pick_kmax(k), a0, h->row_cache, (hipStream_t)stream);
+    hipError_t e = sc::launch_omp_batch(h->dev, p, sc::pick_kmax(k), a0, row_cache_for(h, flags), (hipStream_t)stream);
     if (e == hipErrorInvalidValue) return SC_EINVAL;
     if (e != hipSuccess) return set_dev_error("sc_omp_encode_rows", e);
     return SC_OK;

@@ -175,6 +175,7 @@ struct sc_dict_s {
     unsigned long long *stats = nullptr;
     int a0_fp32 = sc::A0_VALU;       // alpha0 stage of the FP32 encoder (tunable)
     int row_cache = 0;               // Gram rows kept in registers by the encoder (tunable: 0 or 4)
+    int row_cache_bf16 = 0;          // the same for the split-BF16 encoder
     sc::DictDev *ddev = nullptr;     // device copy of `dev`
     int restricted_cap = 0;          // restricted-OMP step cap of the learned encoder (0 = k; tunable)
 };

@@ -33,6 +33,7 @@ TRAIN_GRAD_ONLY = 0x2
 TUNE_FP32_CORRELATION = 1
 TUNE_ROW_CACHE = 2
 TUNE_RESTRICTED_CAP = 3
+TUNE_ROW_CACHE_BF16 = 4
 CORR_VALU = 0
 CORR_MFMA = 1
 

@@ -128,6 +128,32 @@ def test_precision_modes_on_near_duplicates(flags, corr):
     print(flags, corr, r, stats)
 
 
+@pytest.mark.parametrize("K", [256, 512])
+def test_row_cache_settings_give_the_same_codes(K):
+    """The row caches of the FP32 and split-BF16 encoders are separate
+    settings; either value leaves the codes unchanged (cached Gram rows are
+    the same values, summed in the same order)."""
+    D = I.random_dictionary(I.rng_for(90 + K), K)
+    X = I.sparse_signals(I.rng_for(91 + K), D, 3000, 6)[0]
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    Xg = torch.from_numpy(X).to(DEV)
+    for flags, key, other in ((0, sc.TUNE_ROW_CACHE, sc.TUNE_ROW_CACHE_BF16),
+                              (sc.PREC_BF16, sc.TUNE_ROW_CACHE_BF16, sc.TUNE_ROW_CACHE)):
+        runs = []
+        for rc in (0, 4):
+            h.set_tuning(key, rc)
+            h.set_tuning(other, 4 - rc)   # the other encoder's setting must not matter
+            assert h.get_tuning(key) == rc
+            out = sc.omp_encode(h, Xg, 12, 1e-3, flags)
+            runs.append([t.cpu().numpy() for t in out])
+        np.testing.assert_array_equal(runs[0][0], runs[1][0])
+        np.testing.assert_array_equal(runs[0][2], runs[1][2])
+        np.testing.assert_allclose(runs[0][1], runs[1][1], rtol=0, atol=1e-6)
+    with pytest.raises(sc.ScError):
+        h.set_tuning(sc.TUNE_ROW_CACHE_BF16, 2)
+    h.destroy()
+
+
 def test_relative_tolerance_and_edge_signals():
     rng = I.rng_for(74)
     D = I.random_dictionary(rng, 256)
