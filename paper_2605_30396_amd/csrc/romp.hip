@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
         vR al;
 #pragma unroll
         for (int e = 0; e < kRCpl; ++e) al[e] = 0.f;
-        constexpr int kCB = 4;   // candidates per batch of loads
+        constexpr int kCB = 2;   // candidates per batch of loads (4 would cost a wave per SIMD at k = 8)
         static_assert((8 * kRCpl) % kCB == 0, "candidate batches");
 #pragma unroll
         for (int b = 0; b < 8 * kRCpl / kCB; ++b) {
