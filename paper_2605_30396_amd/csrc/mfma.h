@@ -44,16 +44,18 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 //   erfc(u) = tt P(tt) exp(-u^2),  tt = 1 / (1 + p u),  u = |t| / sqrt 2 >= 0.
 // For t < 0, Phi(t) = erfc(u)/2 is formed without cancellation.
 __device__ __forceinline__ void phi_and_gauss(float t, float &Phi, float &g) {
-    const float u = fabsf(t) * 0.70710678118654752f;
-    const float tt = __builtin_amdgcn_rcpf(fmaf(0.2904645284900774f, u, 1.f));
-    float P = 1.3867848039238604f;
-    P = fmaf(P, tt, -2.857302961792132f);
-    P = fmaf(P, tt, 3.358415107698794f);
-    P = fmaf(P, tt, -1.7159331110633307f);
-    P = fmaf(P, tt, 0.7366526417252831f);
-    P = fmaf(P, tt, 0.091383530954993f);
-    g = __builtin_amdgcn_exp2f(-u * u * 1.4426950408889634f);   // exp(-t^2 / 2)
-    const float h = 0.5f * tt * P * g;                            // erfc(u) / 2
+    // 1 / sqrt 2 is folded into p (tt = 1 / (1 + (p / sqrt 2) |t|)), the
+    // polynomial's coefficients are halved (an exact scaling, so P * tt * g
+    // is erfc(u) / 2 with the same rounding), and exp(-u^2) = exp(-t^2 / 2)
+    const float tt = __builtin_amdgcn_rcpf(fmaf(0.2053894377894869f, fabsf(t), 1.f));
+    float P = 0.6933924019619302f;
+    P = fmaf(P, tt, -1.428651480896066f);
+    P = fmaf(P, tt, 1.679207553849397f);
+    P = fmaf(P, tt, -0.8579665555316653f);
+    P = fmaf(P, tt, 0.36832632086264155f);
+    P = fmaf(P, tt, 0.0456917654774965f);
+    g = __builtin_amdgcn_exp2f(t * t * -0.7213475204444817f);   // exp(-t^2 / 2) = 2^(-t^2 log2(e) / 2)
+    const float h = tt * P * g;                                  // erfc(u) / 2
     Phi = t >= 0.f ? 1.f - h : h;
 }
 
