@@ -38,6 +38,14 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Two FP32 values rounded to BF16 (round to nearest even) in one packed
+// conversion: a in the low half, b in the high half.
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pack2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){a, b}, bf16x2));
+}
+
 // Phi(t), the standard normal CDF, and exp(-t^2/2), via a rational fit of
 // erfc of the form of Abramowitz & Stegun 7.1.26 with coefficients fitted for
 // this library (max |error| of erf ~1.2e-8 before FP32 rounding):

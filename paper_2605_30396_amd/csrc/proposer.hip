@@ -97,13 +97,9 @@ __device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int 
         for (int g = 0; g < 4; ++g) {
             const int i0 = 32 * wave + 8 * g + 4 * (lane >> 5);
             const float4 bb = *reinterpret_cast<const float4 *>(bias + i0);
-            uint32_t h0 = bf16_bits(gelu_f(acc[n][4 * g + 0] + bb.x));
-            uint32_t h1 = bf16_bits(gelu_f(acc[n][4 * g + 1] + bb.y));
-            uint32_t h2 = bf16_bits(gelu_f(acc[n][4 * g + 2] + bb.z));
-            uint32_t h3 = bf16_bits(gelu_f(acc[n][4 * g + 3] + bb.w));
             uint2 pk;
-            pk.x = h0 | (h1 << 16);
-            pk.y = h2 | (h3 << 16);
+            pk.x = bf16_pack2(gelu_f(acc[n][4 * g + 0] + bb.x), gelu_f(acc[n][4 * g + 1] + bb.y));
+            pk.y = bf16_pack2(gelu_f(acc[n][4 * g + 2] + bb.z), gelu_f(acc[n][4 * g + 3] + bb.w));
             *reinterpret_cast<uint2 *>(Hout + j * kHS + i0) = pk;
         }
     }
