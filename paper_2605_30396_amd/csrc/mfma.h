@@ -51,10 +51,10 @@ __device__ __forceinline__ uint32_t bf16_pack2(float a, float b) {
 // this library (max |error| of erf ~1.2e-8 before FP32 rounding):
 //   erfc(u) = tt P(tt) exp(-u^2),  tt = 1 / (1 + p u),  u = |t| / sqrt 2 >= 0.
 // For t < 0, Phi(t) = erfc(u)/2 is formed without cancellation.
-__device__ __forceinline__ void phi_and_gauss(float t, float &Phi, float &g) {
-    // 1 / sqrt 2 is folded into p (tt = 1 / (1 + (p / sqrt 2) |t|)), the
-    // polynomial's coefficients are halved (an exact scaling, so P * tt * g
-    // is erfc(u) / 2 with the same rounding), and exp(-u^2) = exp(-t^2 / 2)
+// h = erfc(u) / 2 = Phi(-|t|) and g = exp(-t^2 / 2).  1 / sqrt 2 is folded
+// into p (tt = 1 / (1 + (p / sqrt 2) |t|)) and the polynomial's coefficients
+// are halved (an exact scaling, so tt * P * g is erfc(u) / 2 directly).
+__device__ __forceinline__ void erfc_half_and_gauss(float t, float &h, float &g) {
     const float tt = __builtin_amdgcn_rcpf(fmaf(0.2053894377894869f, fabsf(t), 1.f));
     float P = 0.6933924019619302f;
     P = fmaf(P, tt, -1.428651480896066f);
@@ -62,16 +62,22 @@ __device__ __forceinline__ void phi_and_gauss(float t, float &Phi, float &g) {
     P = fmaf(P, tt, -0.8579665555316653f);
     P = fmaf(P, tt, 0.36832632086264155f);
     P = fmaf(P, tt, 0.0456917654774965f);
-    g = __builtin_amdgcn_exp2f(t * t * -0.7213475204444817f);   // exp(-t^2 / 2) = 2^(-t^2 log2(e) / 2)
-    const float h = tt * P * g;                                  // erfc(u) / 2
+    g = __builtin_amdgcn_exp2f(t * t * -0.7213475204444817f);   // 2^(-t^2 log2(e) / 2)
+    h = tt * P * g;
+}
+
+__device__ __forceinline__ void phi_and_gauss(float t, float &Phi, float &g) {
+    float h;
+    erfc_half_and_gauss(t, h, g);
     Phi = t >= 0.f ? 1.f - h : h;
 }
 
-// GELU(t) = t Phi(t) (the exact, erf form).
+// GELU(t) = t Phi(t) (the exact, erf form) = max(t, 0) - |t| h for either
+// sign of t, with h = Phi(-|t|).
 __device__ __forceinline__ float gelu_f(float t) {
-    float Phi, g;
-    phi_and_gauss(t, Phi, g);
-    return t * Phi;
+    float h, g;
+    erfc_half_and_gauss(t, h, g);
+    return fmaf(-fabsf(t), h, fmaxf(t, 0.f));
 }
 
 // d/dt GELU = Phi(t) + t phi(t),  phi(t) = exp(-t^2/2) / sqrt(2 pi).
