@@ -50,7 +50,7 @@ def test_plain_small_shared_directions_from_oracle_codes():
     assert np.abs(rgb - exp).max() <= ATOL
 
 
-@pytest.mark.parametrize("K,k", [(256, 8), (90, 12), (512, 12), (1024, 16), (64, 1)])
+@pytest.mark.parametrize("K,k", [(256, 8), (90, 12), (512, 12), (630, 12), (640, 12), (1024, 16), (64, 1)])
 def test_per_signal_directions(K, k):
     rng = I.rng_for(80 + K + k)
     D = I.random_dictionary(rng, K)
