@@ -84,10 +84,10 @@ def test_csc_radiance_equals_padded_radiance_and_oracle():
     h.destroy()
 
 
-@pytest.mark.parametrize("K", [90, 256, 1000])
+@pytest.mark.parametrize("K", [90, 256, 630, 640, 1000])
 def test_gaussian_colour_step(K):
     """The fused colour: camera-to-Gaussian direction, C0 DC term, compressed
-    SH, +0.5, clamp at 0 (K = 1000 reads D from global memory, not LDS)."""
+    SH, +0.5, clamp at 0 (K = 640 and 1000 read D from global memory, not LDS)."""
     N = 2500
     D, X, h, (idx, coef, count, resid) = codes(N, K, 12, 520 + K, eps=1e-2, bad=(3,))
     rng = np.random.default_rng(K)
