@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kOmpThreads) void omp_multi_kernel(MultiArgs a) {
         const int nt = (int)min<int64_t>(T, sd.N - s0);
 #define SC_BODY(EI, EE, KK)                                                                            \
     case 4 * EI + KK / 4 - 1:                                                                          \
-        omp_tile<EE, KK, T, false, RCQ>(dict, p, MODE, s0, nt, smem_raw, tidv, tally);                 \
+        omp_tile<EE, KK, T, false, (EE <= 4 ? RCQ : 0)>(dict, p, MODE, s0, nt, smem_raw, tidv, tally); \
         break;
         switch (sd.cls) {
             SC_BODY(0, 1, 4) SC_BODY(0, 1, 8) SC_BODY(0, 1, 12) SC_BODY(0, 1, 16)
