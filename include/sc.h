@@ -119,12 +119,19 @@ int sc_dict_gram(sc_dict h, float *G_out, void *stream);
  * Gram-column update of the correlations, and finally a refit of the
  * coefficients from D_I^T x.
  *
- * Precision (flags): FP32 throughout by default.  SC_PREC_BF16 computes the
- * correlations on BF16 MFMA with FP32 accumulation (residual form: the
- * correlations of the FP32 residual are recomputed every step) while the
- * Cholesky factor, the stop test and the refit stay FP32.  Supports whose
- * Cholesky condition estimate (max l_ii / min l_ii)^2 exceeds 1e3 are refit
- * in FP64 unless SC_NO_FP64_REFIT.
+ * Precision (flags): FP32 throughout by default.  SC_PREC_BF16 forms
+ * alpha0 = D^T x on BF16 MFMA with FP32 accumulation as a split product,
+ * D = Dh + Dl and x = xh + xl in BF16, alpha0 = Dh xh + Dl xh + Dh xl (error
+ * <= 1.6e-5 ||x|| per unit atom); the correlations are then updated in Gram
+ * form in FP32 as in the default path.  Before each selection, every atom
+ * whose |correlation| lies within twice that error bound of the best one is
+ * re-correlated in FP32 from x (its alpha0 replaced by the exact value), so
+ * the selections are those of the FP32 correlations and the chosen atom's
+ * alpha0, which the coefficients, the tracked residual and the stop test
+ * use, is FP32.  The Cholesky factor, the stop test and the final
+ * coefficients stay FP32.  Supports whose Cholesky condition estimate
+ * (max l_ii / min l_ii)^2 exceeds 1e3 are refit in FP64 unless
+ * SC_NO_FP64_REFIT.
  *
  *   X      device N x d float32          idx   device N x k int32 (out)
  *   N      >= 0 (0: no device work, the  coef  device N x k float32 (out)
@@ -145,7 +152,8 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
  *   SC_TUNE_ROW_CACHE  Gram rows of the first selected atoms kept in
  *     registers by the encoder: 0 (default for K > 256: every row re-read
  *     from cache memory when the correlations are formed) or 4 (applies to
- *     K <= 512).
+ *     K <= 512 here; the batched encoder applies its own row_cache setting to
+ *     dictionaries of K <= 256 only).
  *   SC_TUNE_ROW_CACHE_BF16  the same choice for the split-BF16 form
  *     (SC_PREC_BF16), whose encoder holds more registers, so its best value
  *     can differ.
@@ -288,7 +296,9 @@ int sc_screen_topk(sc_dict h, const float *X, int64_t N, int n_cand, int32_t *ca
  * sc_omp_encode_restricted -- step 2 and 3 of sc_omp_encode_learned on their
  * own: Batch-OMP of each signal restricted to its candidate atoms (cand,
  * N x n_cand, sorted by atom index, a row starting with -1 = no candidates),
- * explicit-residual acceptance; accepted codes are written to idx/coef/
+ * explicit-residual acceptance.  A candidate entry outside [0, K) is read as
+ * -1 (no candidate), so a row whose first entry is out of range takes the
+ * fallback like a row of -1.  Accepted codes are written to idx/coef/
  * count/resid, the other signals' indices are appended to miss_rows
  * (device int32[N]) and counted in *miss_count (device int32, zeroed by the
  * call).  The order of miss_rows varies from call to call (rows are appended
@@ -305,7 +315,10 @@ int sc_omp_encode_restricted(sc_dict h, const float *X, int64_t N, int k, float 
  * the rows listed in rows[0 .. *nrows) of X (nrows is a DEVICE int32, read by
  * the kernel, so the list can come from sc_omp_encode_restricted without a
  * host round trip); outputs are written at those rows.  max_rows bounds
- * *nrows (it sizes the launch).
+ * *nrows (it sizes the launch), and the call requires max_rows <= the number
+ * of rows of X (it is the number of rows whose outputs may be written).  A
+ * list entry outside [0, max_rows) is skipped (nothing is read or written
+ * for it).
  */
 int sc_omp_encode_rows(sc_dict h, const float *X, const int32_t *rows, const int32_t *nrows, int64_t max_rows, int k,
                        float eps, int flags, int32_t *idx, float *coef, int32_t *count, float *resid, void *stream);
@@ -469,7 +482,9 @@ typedef struct {
  * sc_batch_tuning: launch shape of the batched encoder (results do not
  * depend on it beyond FP32 rounding order).
  *   tile       signals per workgroup tile: 16 or 32 (0 = 16)
- *   row_cache  Gram rows kept in registers: 0 or 4
+ *   row_cache  Gram rows kept in registers: 0 or 4 (4 applies to the
+ *              scenes with K <= 256; larger dictionaries re-read every row,
+ *              which keeps the merged kernel within 128 registers)
  *   wg_per_cu  persistent workgroups per compute unit, 0 = as many as fit
  *   order      SC_ORDER_COST: scenes taken most expensive tile first;
  *              SC_ORDER_GIVEN: in the order of the array

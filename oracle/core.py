@@ -39,7 +39,7 @@ def _load():
     lib = C.CDLL(_SO)
     P = C.c_void_p
     lib.orc_omp.argtypes = [P, C.c_int, C.c_int, P, C.c_int64, C.c_int, C.c_double, C.c_int,
-                            P, C.c_int, P, P, P, P, P, P, P, C.c_int]
+                            P, C.c_int, P, P, P, P, P, P, P, P, P, C.c_int]
     lib.orc_omp.restype = C.c_int
     lib.orc_sh_basis.argtypes = [P, C.c_int64, C.c_int, P]
     lib.orc_sh_basis.restype = None
@@ -68,7 +68,9 @@ def omp(D, X, k, eps=0.0, relative=False, nthreads=None, with_margin=False, cand
     count (N,) int32, resid (N,) float64 = ||x - D_I gamma||_2 and, if asked,
     margin (N,) = min over steps of (|c|_(1) - |c|_(2)) / ||r|| and gap (N,)
     = min over steps of |c|_(1) - |c|_(2), and rpath
-    (N, k+1): the residual norm before each selection and at the end.
+    (N, k+1): the residual norm before each selection and at the end, with
+    mpath and gpath (N, k): each step's relative margin and absolute gap
+    (NaN past the end).
     cand: optional (N, n_cand) int32 -- restrict each signal's pursuit to
     its listed atoms."""
     lib = _load()
@@ -84,13 +86,16 @@ def omp(D, X, k, eps=0.0, relative=False, nthreads=None, with_margin=False, cand
     margin = np.empty(N, np.float64) if with_margin else None
     gap = np.empty(N, np.float64) if with_margin else None
     rpath = np.empty((N, k + 1), np.float64) if with_path else None
+    mpath = np.empty((N, k), np.float64) if with_path else None
+    gpath = np.empty((N, k), np.float64) if with_path else None
     n_cand = 0
     if cand is not None:
         cand = np.ascontiguousarray(cand, np.int32)
         assert cand.shape[0] == N
         n_cand = cand.shape[1]
     rc = lib.orc_omp(_p(D), d, K, _p(X), N, int(k), float(eps), int(bool(relative)), _p(cand), n_cand,
-                     _p(idx), _p(coef), _p(count), _p(resid), _p(margin), _p(rpath), _p(gap), _threads(nthreads))
+                     _p(idx), _p(coef), _p(count), _p(resid), _p(margin), _p(rpath), _p(gap), _p(mpath), _p(gpath),
+                     _threads(nthreads))
     if rc != 0:
         raise ValueError("orc_omp: invalid arguments")
     out = dict(idx=idx, coef=coef, count=count, resid=resid)
@@ -99,6 +104,8 @@ def omp(D, X, k, eps=0.0, relative=False, nthreads=None, with_margin=False, cand
         out["gap"] = gap
     if with_path:
         out["rpath"] = rpath
+        out["mpath"] = mpath
+        out["gpath"] = gpath
     return out
 
 

@@ -99,6 +99,8 @@ typedef struct {
     double *margin;       /* optional: min over steps of (|c|_(1)-|c|_(2))/||r|| */
     double *rpath;        /* optional N x (k+1): ||r|| after 0..count atoms, NaN after */
     double *gap;          /* optional: min over steps of |c|_(1) - |c|_(2) (absolute) */
+    double *mpath;        /* optional N x k: step t's (|c|_(1)-|c|_(2))/||r||, NaN past the end */
+    double *gpath;        /* optional N x k: step t's |c|_(1) - |c|_(2), NaN past the end */
     int64_t lo, hi;
 } omp_job;
 
@@ -120,6 +122,11 @@ static void omp_one(const omp_job *J, int64_t s, double *ws, unsigned char *used
     double *path = J->rpath ? J->rpath + s * (k + 1) : NULL;
     if (path)
         for (int t = 0; t <= k; ++t) path[t] = NAN;
+    double *mp = J->mpath ? J->mpath + s * k : NULL, *gp = J->gpath ? J->gpath + s * k : NULL;
+    for (int t = 0; t < k; ++t) {
+        if (mp) mp[t] = NAN;
+        if (gp) gp[t] = NAN;
+    }
     if (!finite) {
         J->count[s] = -1;
         J->resid[s] = NAN;
@@ -165,6 +172,8 @@ static void omp_one(const omp_job *J, int64_t s, double *ws, unsigned char *used
         double m = (bv - sv) / rn;
         if (m < marg) marg = m;
         if (bv - sv < gmin) gmin = bv - sv;
+        if (mp) mp[n] = m;
+        if (gp) gp[n] = bv - sv;
         used[best] = 1;
         I[n] = best;
         memcpy(A + (size_t)n * d, J->D + (size_t)best * d, sizeof(double) * d);
@@ -213,12 +222,14 @@ static void *omp_worker(void *arg)
  * count N, resid N (explicit ||x - D_I gamma||), margin N (optional, may be
  * NULL), rpath N x (k+1) (optional: the residual norm before each selection
  * and at the end, NaN past the end), gap N (optional: min over steps of the
- * absolute gap between the two largest |correlations|).  Returns 0, or -1 on
- * bad arguments.
+ * absolute gap between the two largest |correlations|), mpath and gpath
+ * N x k (optional: the relative margin and the absolute gap of each step,
+ * NaN past the end).  Returns 0, or -1 on bad arguments.
  */
 int orc_omp(const float *D_atoms, int d, int K, const float *X, int64_t N, int k, double eps,
             int relative, const int32_t *cand, int n_cand, int32_t *idx, double *coef,
-            int32_t *count, double *resid, double *margin, double *rpath, double *gap, int nthreads)
+            int32_t *count, double *resid, double *margin, double *rpath, double *gap,
+            double *mpath, double *gpath, int nthreads)
 {
     if (d <= 0 || K <= 0 || k <= 0 || k > d || N < 0 || !(eps >= 0.0)) return -1;
     if (cand && n_cand <= 0) return -1;
@@ -230,7 +241,7 @@ int orc_omp(const float *D_atoms, int d, int K, const float *X, int64_t N, int k
     omp_job *jobs = (omp_job *)malloc(sizeof(omp_job) * nthreads);
     for (int t = 0; t < nthreads; ++t) {
         omp_job J = {Dd, d, K, k, eps, relative, X, cand, n_cand, idx, coef, count, resid, margin,
-                     rpath, gap, N * t / nthreads, N * (t + 1) / nthreads};
+                     rpath, gap, mpath, gpath, N * t / nthreads, N * (t + 1) / nthreads};
         jobs[t] = J;
         pthread_create(&th[t], NULL, omp_worker, &jobs[t]);
     }

@@ -77,10 +77,11 @@ struct OmpTally {
 // feature-major Xt[i][s]; features >= d and columns >= nt are zero.
 template <int T>
 __device__ __forceinline__ void load_tile(const OmpParams &p, int d, int64_t s0, int nt, float *Xt, int tid) {
-    if (p.rows) {
+    if (p.rows) {   // a listed row outside [0, N) reads as zeros (and is not encoded)
         for (int f = tid; f < nt * d; f += kOmpThreads) {
             const int s = f / d, i = f - s * d;
-            Xt[i * xt_stride(T) + s] = p.X[(int64_t)p.rows[s0 + s] * d + i];
+            const int64_t r = p.rows[s0 + s];
+            Xt[i * xt_stride(T) + s] = (uint64_t)r < (uint64_t)p.N ? p.X[r * d + i] : 0.f;
         }
     } else {
         const float *__restrict__ Xtile = p.X + s0 * d;
@@ -263,9 +264,11 @@ __device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)
 }
 
 // Encodes signal `sig` (column s of the tile) with one wave.  kSplit: alpha0
-// holds the split-BF16 correlations, and alpha0_j of a selected atom is
-// recomputed in FP32 from the signal, so the coefficients, the tracked
-// residual and the stop test carry no BF16 error.
+// holds the split-BF16 correlations; before each selection, every atom that
+// could still beat the best one within the split-BF16 error bound is
+// re-correlated in FP32 from the signal, so the selections are those of the
+// FP32 correlations, and the chosen atom's alpha0 (which the coefficients,
+// the tracked residual and the stop test use) is exact FP32.
 // RCQ: the Gram rows of the atoms of the first RCQ steps are kept in
 // registers (RCQ * E VGPRs).  The row of the newest atom is fetched as soon
 // as the atom is chosen and held for the next step; older rows are re-read
@@ -301,6 +304,12 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     const float eps2 = eps_abs * eps_abs;
     const float band = 1e-5f * xx;     // FP32 uncertainty of the tracked ||r||^2
     const float brk = 1e-6f * xnorm;   // residual orthogonal to every atom
+    // Bound on the error of a split-BF16 alpha0 entry (unit atom): the terms
+    // the three products leave out are each <= 2^-18 |a_i x_i|, so <= 3 2^-18
+    // ||x|| in all (Cauchy-Schwarz), plus FP32 accumulation of 64 products
+    // (<= 64 2^-24 ||x||): 1.52e-5 ||x||.
+    const float split_err = 1.6e-5f * xnorm;
+    uint32_t exact = 0u;               // bit e: a0[e] is the FP32 correlation
 
     // Key bit 31 marks an atom still selectable: any such key beats every
     // retired or padding atom, whatever their magnitude bits.
@@ -440,7 +449,48 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         uint32_t best = 0u;
 #pragma unroll
         for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
-        const uint32_t kb = wave_max_u32(best);
+        uint32_t kb = wave_max_u32(best);
+        if constexpr (kSplit) {
+            // Every selectable atom whose split-BF16 alpha0 may still be off
+            // by up to split_err and whose |alpha| lies within 2 split_err of
+            // the best is re-correlated in FP32 first (alpha0 and alpha take
+            // the exact value), then the best is found again: an atom left
+            // out is below the best by more than its error, so the choice is
+            // the one the FP32 correlations give.
+            for (;;) {
+                const float thr = __uint_as_float(kb & kKeyMag) - 2.f * split_err;
+                uint32_t cm = 0u;
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    cm |= ((kid[e] & kKeyLive) && !((exact >> e) & 1u) && fabsf(al[e]) >= thr) ? (1u << e) : 0u;
+                uint64_t lanes = ballot(cm != 0u);
+                if (lanes == 0) break;
+                while (lanes) {
+                    const int l = __ffsll((unsigned long long)lanes) - 1;
+                    lanes &= lanes - 1;
+                    uint32_t cl = (uint32_t)__builtin_amdgcn_readlane((int)cm, l);
+                    while (cl) {
+                        const int e = __ffs(cl) - 1;
+                        cl &= cl - 1;
+                        const float z = wave_sum(lane < d ? Dg[(size_t)(l * E + e) * d + dl] * xv : 0.f);
+                        if (lane == l) {
+#pragma unroll
+                            for (int q = 0; q < E; ++q) {
+                                if (q == e) {
+                                    al[q] += z - a0[q];
+                                    a0[q] = z;
+                                }
+                            }
+                            exact |= 1u << e;
+                        }
+                    }
+                }
+                best = 0u;
+#pragma unroll
+                for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
+                kb = wave_max_u32(best);
+            }
+        }
         if (!(__uint_as_float(kb & kKeyMag) > brk)) {
             active = false;
             continue;
@@ -473,10 +523,15 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         const float ell = __builtin_amdgcn_sqrtf(l2);
         const float inv = __builtin_amdgcn_rcpf(ell);
         float zj;
-        if constexpr (kSplit)
-            zj = wave_sum(lane < d ? Dg[(size_t)j * d + lane] * xv : 0.f);
-        else
+        if constexpr (kSplit) {   // the chosen atom's alpha0 is exact (re-correlated above)
+            const int je = j % E;
+            float mine = a0[0];
+#pragma unroll
+            for (int q = 1; q < E; ++q) mine = q == je ? a0[q] : mine;
+            zj = readlane_f(mine, j / E);
+        } else {
             zj = A0[s * a0_stride(Kp) + j];
+        }
         const float cn = (zj - wc) * inv;
         rr = readfirstlane_f(fmaf(-cn, cn, rr));
         lmax = fmaxf(lmax, ell);
@@ -552,6 +607,7 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
     __syncthreads();
     for (int s = wave; s < nt; s += kOmpWaves) {
         const int64_t sig = p.rows ? (int64_t)p.rows[s0 + s] : s0 + s;
+        if (p.rows && (uint64_t)sig >= (uint64_t)p.N) continue;   // out-of-range list entry: skipped
         if (kSplitOK && split)
             omp_pursuit<E, KMAX, kSplitOK, T, RCQ>(dict, p, sig, s, Xt, A0, lane, tally);
         else
@@ -673,7 +729,7 @@ __device__ __forceinline__ unsigned long long refit_scan(const DictDev &dict, co
         int cnt = 0;
         if (i < Nsig) {
             sig = p.rows ? (int64_t)p.rows[i] : i;
-            cnt = p.count[sig];
+            if ((uint64_t)sig < (uint64_t)p.N) cnt = p.count[sig];   // out-of-range list entries are skipped
         }
         uint64_t flagged = ballot(cnt < -1);
         while (flagged) {

@@ -152,13 +152,16 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
             const int f = g + 8 * q;
             xr[q] = (valid && f < d) ? p.X[sig * d + f] : 0.f;
         }
+        // a candidate outside [0, K) reads as -1 (no candidate)
         int cid[kRCpl];
 #pragma unroll
         for (int e = 0; e < kRCpl; ++e) {
             const int q = g * kRCpl + e;
-            cid[e] = (valid && q < nc) ? p.cand[sig * nc + q] : -1;
+            const int c = (valid && q < nc) ? p.cand[sig * nc + q] : -1;
+            cid[e] = (unsigned)c < (unsigned)dict.K ? c : -1;
         }
-        const int first = valid ? p.cand[sig * nc] : 0;
+        int first = valid ? p.cand[sig * nc] : 0;
+        first = (unsigned)first < (unsigned)dict.K ? first : -1;
         float xx_part = 0.f;
         bool fin = true;
 #pragma unroll

@@ -301,3 +301,47 @@ def test_full_size_sampled_learned_encoder():
     assert abs(frac - ref_frac) <= 0.03
     p.destroy()
     h.destroy()
+
+
+def test_out_of_range_candidates_and_rows_are_ignored():
+    """Caller-supplied lists are range-checked in the kernels: a candidate id
+    outside [0, K) reads as -1 (a row whose first entry is out of range has no
+    candidates and goes to the fallback list), and a fallback-list entry
+    outside [0, max_rows) is skipped (no output is written for it)."""
+    K, k, eps = 256, 8, 1e-2
+    rng = I.rng_for(240)
+    D = I.random_dictionary(rng, K)
+    X, _, _ = I.sparse_signals(rng, D, 64, 4, 1e-3)
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    Xg = torch.from_numpy(X).to(DEV)
+    cand = sc.screen_topk(h, Xg, 24).cpu().numpy()
+    bad = cand.copy()
+    bad[0, :] = K + 5                  # no usable candidate at all
+    bad[1, 0] = 1 << 30                # first entry out of range
+    bad[2, 5:] = -7                    # only the first five candidates usable
+    bad[3, 10] = K                     # one entry just past the dictionary
+    idx, coef, count, resid, mr, mc = sc.omp_encode_restricted(h, Xg, k, eps, torch.from_numpy(bad).to(DEV))
+    torch.cuda.synchronize()
+    miss = set(mr[:int(mc.item())].cpu().numpy().tolist())
+    assert {0, 1} <= miss
+    cnt, gi = count.cpu().numpy(), idx.cpu().numpy()
+    for i in range(len(X)):
+        if i in miss:
+            continue
+        use = set(bad[i][(bad[i] >= 0) & (bad[i] < K)].tolist())
+        assert set(gi[i, :cnt[i]].tolist()) <= use, i
+    # a fallback list with out-of-range entries: only the listed in-range rows are written
+    rows = torch.tensor([3, -1, 64, 1 << 30, 7, 63], dtype=torch.int32, device=DEV)
+    nrows = torch.tensor([rows.numel()], dtype=torch.int32, device=DEV)
+    out = (torch.full((64, k), -9, dtype=torch.int32, device=DEV), torch.full((64, k), 9.0, device=DEV),
+           torch.full((64,), -9, dtype=torch.int32, device=DEV), torch.full((64,), 9.0, device=DEV))
+    sc.omp_encode_rows(h, Xg, rows, nrows, 64, k, eps, out)
+    plain = [t.cpu().numpy() for t in sc.omp_encode(h, Xg, k, eps)]
+    torch.cuda.synchronize()
+    o = [t.cpu().numpy() for t in out]
+    written = [3, 7, 63]
+    for a, b in zip(o, plain):
+        np.testing.assert_array_equal(a[written], b[written])
+    untouched = np.setdiff1d(np.arange(64), written)
+    assert np.all(o[2][untouched] == -9) and np.all(o[0][untouched] == -9)
+    h.destroy()

@@ -112,8 +112,10 @@ def test_dictionary_and_sparsity_shapes(K, k, eps, s, flags, corr):
     D = I.random_dictionary(rng, K)
     X, _, _ = I.sparse_signals(rng, D, 2000 + 5, s, 1e-3)
     g, _ = encode(D, X, k, eps, flags, corr)
-    bf = bool(flags & sc.PREC_BF16)
-    r = compare_codes(D, X, k, eps, g, min_sep_frac=0.0 if bf else 0.2, bf16=bf)
+    # every mode under the same rule: at least 70% of the oracle's selections
+    # lie in unique prefixes here (48% of the signals are well separated at
+    # K = 48, k = 32, at least 78% elsewhere)
+    r = compare_codes(D, X, k, eps, g, min_sep_frac=0.4 if k == 32 else 0.7, min_step_frac=0.7)
     print(K, k, eps, flags, corr, r)
 
 
@@ -123,8 +125,7 @@ def test_precision_modes_on_near_duplicates(flags, corr):
     workload's generator, 6000 signals)."""
     w = I.workload_precision(N=6000)
     g, stats = encode(w["D"], w["X"], 12, 0.0, flags, corr)
-    bf = bool(flags & sc.PREC_BF16)
-    r = compare_codes(w["D"], w["X"], 12, 0.0, g, min_sep_frac=0.0 if bf else 0.2, bf16=bf)
+    r = compare_codes(w["D"], w["X"], 12, 0.0, g, min_sep_frac=0.7, min_step_frac=0.85)
     print(flags, corr, r, stats)
 
 

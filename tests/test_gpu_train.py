@@ -67,7 +67,15 @@ def test_bf16_gradients_match_oracle():
         assert err <= 2e-2, (n, err)
 
 
-def test_adam_step_matches_oracle():
+def test_adam_steps_match_oracle():
+    """Three FP32 training steps of the GPU against the oracle's own
+    trajectory from the same start: at every step the oracle takes its FP64
+    gradients at its own parameters and applies Adam with its moments carried
+    over (nothing of the GPU's state enters it).  Step t's update is compared
+    on the parameters whose oracle gradient is clear of zero at every step so
+    far (there the sign of each moment is fixed), at 2e-3 lr; a bias
+    correction stuck at t = 1 or moments overwritten each step change those
+    updates by 25-35% from t = 2 on."""
     K, B = 128, 64
     D, X, ref, P = problem(K=K, N=B, seed=303)
     p = sc.proposer_create(45, 256, K)
@@ -75,23 +83,30 @@ def test_adam_step_matches_oracle():
     Xg = torch.from_numpy(X).to(DEV)
     sup = torch.from_numpy(ref["idx"]).to(DEV)
     cnt = torch.from_numpy(ref["count"]).to(DEV)
-    lr = 1e-3
-    for step in (1, 2):
-        before = sc.unpack_params(p.get_params().cpu(), 45, 256, K)
+    Y = oracle.multi_hot(ref["idx"], ref["count"], K)
+    lr = 1e-4
+    pref = {n: np.asarray(v, np.float64) for n, v in P.items()}
+    m = {n: np.zeros_like(v) for n, v in pref.items()}
+    v = {n: np.zeros_like(x) for n, x in pref.items()}
+    clear = {n: np.ones(x.shape, bool) for n, x in pref.items()}
+    before = {n: t.numpy().astype(np.float64) for n, t in sc.unpack_params(p.get_params().cpu(), 45, 256, K).items()}
+    for step in (1, 2, 3):
+        _, gref = oracle.mlp_loss_and_grads(pref, X, Y, 1.0)
+        nref = oracle.adam_step(pref, gref, m, v, step, lr=lr)
         sc.proposer_train_step(p, Xg, sup, cnt, B, lr=lr, flags=sc.TRAIN_FP32)
-        after = sc.unpack_params(p.get_params().cpu(), 45, 256, K)
-        if step == 1:
-            # first step: the update is lr * g / (|g| + eps_hat) for each parameter
-            Y = oracle.multi_hot(ref["idx"], ref["count"], K)
-            _, gref = oracle.mlp_loss_and_grads({n: v.numpy() for n, v in before.items()}, X, Y, 1.0)
-            m = {n: np.zeros_like(v) for n, v in gref.items()}
-            v = {n: np.zeros_like(x) for n, x in gref.items()}
-            exp = oracle.adam_step({n: t.numpy() for n, t in before.items()}, gref, m, v, 1, lr=lr)
-            for n in exp:
-                upd_g = after[n].numpy().astype(np.float64) - before[n].numpy()
-                upd_r = exp[n] - before[n].numpy()
-                big = np.abs(gref[n]) > 1e-3 * np.abs(gref[n]).max()   # sign(g) clear of eps
-                assert np.max(np.abs(upd_g[big] - upd_r[big])) <= 1e-3 * lr, n
+        after = {n: t.numpy().astype(np.float64)
+                 for n, t in sc.unpack_params(p.get_params().cpu(), 45, 256, K).items()}
+        worst = 0.0
+        for n in nref:
+            clear[n] &= np.abs(gref[n]) > 1e-2 * np.abs(gref[n]).max()
+            assert clear[n].mean() > 0.2, (n, step, clear[n].mean())
+            upd_g = (after[n] - before[n])[clear[n]]
+            upd_r = (nref[n] - pref[n])[clear[n]]
+            err = np.max(np.abs(upd_g - upd_r)) / lr
+            worst = max(worst, err)
+            assert err <= 2e-3, (n, step, err)
+        print(f"step {step}: worst update error {worst:.2e} lr")
+        pref, before = nref, after
     p.destroy()
 
 

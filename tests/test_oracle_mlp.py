@@ -82,6 +82,38 @@ def test_adam_first_step_is_signed_lr():
     np.testing.assert_allclose(out["w"], [0.9, -1.9, 3.0], rtol=1e-12)
 
 
+def test_adam_constant_gradient_is_signed_lr_at_every_step():
+    """With a constant gradient g the moments are m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected ratio is g / |g| at every step
+    t: each update is -lr sign(g).  Moments overwritten instead of accumulated,
+    or a bias correction stuck at t = 1, give 0.74 lr or 1.34 lr at t = 2."""
+    g = {"w": np.array([0.5, -2.0, 1e-3])}
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    m = {"w": np.zeros(3)}
+    v = {"w": np.zeros(3)}
+    for t in range(1, 6):
+        new = oracle.adam_step(p, g, m, v, t, lr=0.1, eps=1e-30)
+        np.testing.assert_allclose(new["w"] - p["w"], [-0.1, 0.1, -0.1], rtol=1e-12)
+        p = new
+
+
+def test_adam_three_steps_worked_by_hand():
+    """b1 = 1/2, b2 = 3/4, lr = 1/10, gradients 1, 3, -2 (eps negligible):
+      t = 1: m = 1/2, v = 1/4; m^ = 1, v^ = 1 -> update -1/10
+      t = 2: m = 1/4 + 3/2 = 7/4, v = 3/16 + 9/4 = 39/16;
+             m^ = (7/4) / (3/4) = 7/3, v^ = (39/16) / (7/16) = 39/7 -> update -(7/3) / sqrt(39/7) / 10
+      t = 3: m = 7/8 - 1 = -1/8, v = 117/64 + 1 = 181/64;
+             m^ = (-1/8) / (7/8) = -1/7, v^ = (181/64) / (37/64) = 181/37 -> update (1/7) / sqrt(181/37) / 10"""
+    p = {"w": np.array([0.0])}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    expected = [-0.1, -(7 / 3) / np.sqrt(39 / 7) / 10, (1 / 7) / np.sqrt(181 / 37) / 10]
+    for t, (gv, de) in enumerate(zip((1.0, 3.0, -2.0), expected), start=1):
+        new = oracle.adam_step(p, {"w": np.array([gv])}, m, v, t, lr=0.1, beta1=0.5, beta2=0.75, eps=1e-30)
+        np.testing.assert_allclose(new["w"] - p["w"], [de], rtol=1e-13)
+        p = new
+
+
 def test_topk_order_and_ties():
     z = np.array([[0.1, 0.5, 0.5, -1.0, 0.5, 0.2]])
     np.testing.assert_array_equal(oracle.topk_lowest_index(z, 4), [[1, 2, 4, 5]])
