@@ -279,6 +279,29 @@ int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, i
                           size_t ws_bytes, void *stream);
 
 /*
+ * sc_omp_encode_learned_noalloc -- sc_omp_encode_learned for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same computation, with the
+ * library's static device scratch in place of the caller's workspace.
+ *
+ * The scratch is one array of SC_STATIC_SCRATCH_BYTES per GPU, held until the
+ * process ends and shared by every call on that GPU, so calls that overlap in
+ * time on one GPU (on different streams, or from different threads) race and
+ * must be serialised by the caller.  Each call clears what must start at zero.
+ *   N, n_cand  sc_omp_encode_learned_workspace(N, n_cand) must not exceed
+ *              SC_STATIC_SCRATCH_BYTES (N <= 335,541 at n_cand = 24);
+ *              larger sizes return SC_ENOMEM before any device work, with the
+ *              sizes in sc_last_error()
+ *   h          must live on the current device (SC_EINVAL otherwise)
+ * Other arguments, outputs and errors as sc_omp_encode_learned.  No
+ * hipMalloc, hipFree or allocating library call is made.
+ */
+#define SC_STATIC_SCRATCH_BYTES (32u << 20)
+int sc_omp_encode_learned_noalloc(sc_dict h, sc_proposer p, const float *X, int64_t N, int k, float eps, int flags,
+                                  int n_cand, int32_t *idx, float *coef, int32_t *count, float *resid,
+                                  void *stream);
+
+/*
  * sc_screen_topk -- correlation screening, the proposer-free baseline of the
  * learned encoder: for each signal the n_cand atoms of largest |<a_j, x>|
  * (one BF16 MFMA product with the dictionary, FP32 accumulation; exact

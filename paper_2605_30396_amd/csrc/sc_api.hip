@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 
 #include "sc_internal.h"
@@ -528,6 +529,69 @@ int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, i
     const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
     SC_HIP(sc::launch_omp_batch(h->dev, fp, kmax, a0, row_cache_for(h, flags), st), "sc_omp_encode_learned (fallback)");
     return SC_OK;
+}
+
+}  // extern "C"
+
+/* ------------------------------------------------------------------ */
+/* the learned encoder without allocation                               */
+/* ------------------------------------------------------------------ */
+
+// Device scratch of sc_omp_encode_learned_noalloc: every GPU the library runs
+// on holds its own copy (at its own address) until the process ends.  In
+// host code `scratch` is only a stand-in for the symbol: the kernels get the
+// device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[SC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device), resolved
+// on the first call for that device.
+int scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return SC_ENODEV;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return set_dev_error("sc_omp_encode_learned_noalloc (scratch address)", e);
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sc_omp_encode_learned_noalloc(sc_dict h, sc_proposer p, const float *X, int64_t N, int k, float eps, int flags,
+                                  int n_cand, int32_t *idx, float *coef, int32_t *count, float *resid,
+                                  void *stream) {
+    if (!h || !p || N < 0 || n_cand < 1 || n_cand > 32) return SC_EINVAL;
+    const size_t need = sc_omp_encode_learned_workspace(N, n_cand);
+    if (need > (size_t)SC_STATIC_SCRATCH_BYTES) {
+        snprintf(g_last_error, sizeof(g_last_error),
+                 "sc_omp_encode_learned_noalloc: N=%lld with n_cand=%d needs %zu bytes of scratch; the static "
+                 "scratch holds %zu",
+                 (long long)N, n_cand, need, (size_t)SC_STATIC_SCRATCH_BYTES);
+        return SC_ENOMEM;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->device) {
+        snprintf(g_last_error, sizeof(g_last_error),
+                 "sc_omp_encode_learned_noalloc: the dictionary lives on device %d, the current device is %d",
+                 h->device, dev);
+        return SC_EINVAL;
+    }
+    void *ws = nullptr;
+    const int rc = scratch_address(dev, &ws);
+    if (rc != SC_OK) return rc;
+    return sc_omp_encode_learned(h, p, X, N, k, eps, flags, n_cand, idx, coef, count, resid, ws,
+                                 (size_t)SC_STATIC_SCRATCH_BYTES, stream);
 }
 
 int sc_omp_encode_restricted(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, const int32_t *cand,

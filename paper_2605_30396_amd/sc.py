@@ -111,6 +111,7 @@ def load():
         "sc_proposer_forward": (I32, [P, P, I64, I32, P, P, P]),
         "sc_omp_encode_learned_workspace": (C.c_size_t, [I64, I32]),
         "sc_omp_encode_learned": (I32, [P, P, P, I64, I32, F32, I32, I32, P, P, P, P, P, C.c_size_t, P]),
+        "sc_omp_encode_learned_noalloc": (I32, [P, P, P, I64, I32, F32, I32, I32, P, P, P, P, P]),
         "sc_omp_encode_restricted": (I32, [P, P, I64, I32, F32, I32, P, I32, P, P, P, P, P, P, P]),
         "sc_screen_topk": (I32, [P, P, I64, I32, P, P]),
         "sc_omp_encode_rows": (I32, [P, P, P, P, I64, I32, F32, I32, P, P, P, P, P]),
@@ -381,6 +382,40 @@ def omp_encode_learned(h: Dictionary, p: Proposer, X, k, eps, n_cand=24, flags=0
     _check("sc_omp_encode_learned", load().sc_omp_encode_learned(
         h.handle, p.handle, _ptr(X), N, int(k), float(eps), int(flags), int(n_cand), _ptr(idx), _ptr(coef),
         _ptr(count), _ptr(resid), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return idx, coef, count, resid
+
+
+# device scratch of sc_omp_encode_learned_noalloc (SC_STATIC_SCRATCH_BYTES in sc.h)
+STATIC_SCRATCH_BYTES = 32 << 20
+
+
+def noalloc_max_signals(n_cand=24):
+    """Largest N that sc_omp_encode_learned_noalloc accepts with n_cand candidates."""
+    lo, hi = 0, STATIC_SCRATCH_BYTES
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if learned_workspace_bytes(mid, n_cand) <= STATIC_SCRATCH_BYTES:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def omp_encode_learned_noalloc(h: Dictionary, p: Proposer, X, k, eps, n_cand=24, flags=0, out=None, stream=None):
+    """sc_omp_encode_learned with the library's static device scratch in place
+    of a workspace (no allocation inside the call; the outputs are allocated
+    here unless `out` is given).  Returns (idx, coef, count, resid)."""
+    _dev_f32(X, "X", 2)
+    N = X.shape[0]
+    if out is None:
+        out = (torch.empty((N, k), dtype=torch.int32, device=X.device),
+               torch.empty((N, k), dtype=torch.float32, device=X.device),
+               torch.empty((N,), dtype=torch.int32, device=X.device),
+               torch.empty((N,), dtype=torch.float32, device=X.device))
+    idx, coef, count, resid = out
+    _check("sc_omp_encode_learned_noalloc", load().sc_omp_encode_learned_noalloc(
+        h.handle, p.handle, _ptr(X), N, int(k), float(eps), int(flags), int(n_cand), _ptr(idx), _ptr(coef),
+        _ptr(count), _ptr(resid), _stream(stream)))
     return idx, coef, count, resid
 
 
