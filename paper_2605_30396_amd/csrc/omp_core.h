@@ -451,20 +451,28 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
         uint32_t kb = wave_max_u32(best);
         if constexpr (kSplit) {
-            // Every selectable atom whose split-BF16 alpha0 may still be off
-            // by up to split_err and whose |alpha| lies within 2 split_err of
-            // the best is re-correlated in FP32 first (alpha0 and alpha take
-            // the exact value), then the best is found again: an atom left
-            // out is below the best by more than its error, so the choice is
-            // the one the FP32 correlations give.
+            // An atom whose split-BF16 alpha0 is not yet exact may be off by
+            // up to split_err.  When another atom besides the best lies within
+            // 2 split_err of it, every such atom that is not exact is
+            // re-correlated in FP32 (alpha0 and alpha take the exact value)
+            // and the best is found again; an atom left out is then below the
+            // best by more than its error, so the choice is the one the FP32
+            // correlations give.  (The best atom itself needs no repair when
+            // it is alone: its alpha0 is recomputed in FP32 below.)
             for (;;) {
                 const float thr = __uint_as_float(kb & kKeyMag) - 2.f * split_err;
                 uint32_t cm = 0u;
+                int near = 0;
 #pragma unroll
-                for (int e = 0; e < E; ++e)
-                    cm |= ((kid[e] & kKeyLive) && !((exact >> e) & 1u) && fabsf(al[e]) >= thr) ? (1u << e) : 0u;
+                for (int e = 0; e < E; ++e) {
+                    const bool in = (kid[e] & kKeyLive) && fabsf(al[e]) >= thr;
+                    near += in ? 1 : 0;
+                    cm |= (in && !((exact >> e) & 1u)) ? (1u << e) : 0u;
+                }
+                const uint64_t one = ballot(near >= 1);
+                if (ballot(near >= 2) == 0 && __popcll(one) <= 1) break;   // the best is alone
                 uint64_t lanes = ballot(cm != 0u);
-                if (lanes == 0) break;
+                if (lanes == 0) break;   // everything in contention is exact already
                 while (lanes) {
                     const int l = __ffsll((unsigned long long)lanes) - 1;
                     lanes &= lanes - 1;
@@ -523,15 +531,10 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         const float ell = __builtin_amdgcn_sqrtf(l2);
         const float inv = __builtin_amdgcn_rcpf(ell);
         float zj;
-        if constexpr (kSplit) {   // the chosen atom's alpha0 is exact (re-correlated above)
-            const int je = j % E;
-            float mine = a0[0];
-#pragma unroll
-            for (int q = 1; q < E; ++q) mine = q == je ? a0[q] : mine;
-            zj = readlane_f(mine, j / E);
-        } else {
+        if constexpr (kSplit)   // the chosen atom's alpha0 in FP32
+            zj = wave_sum(lane < d ? Dg[(size_t)j * d + lane] * xv : 0.f);
+        else
             zj = A0[s * a0_stride(Kp) + j];
-        }
         const float cn = (zj - wc) * inv;
         rr = readfirstlane_f(fmaf(-cn, cn, rr));
         lmax = fmaxf(lmax, ell);
