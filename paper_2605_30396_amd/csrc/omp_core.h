@@ -175,23 +175,23 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ DT, in
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int c = 0; c < CB; ++c) acc[b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // DT holds dt_rows(d) rows, those past d zero, so the next k-step's
+    // operands are read without a bound test.
     const int dk = (d + 3) & ~3;
     float an[NB];
     {
-        const int f = kq;
-        const float *row = DT + (size_t)(f < d ? f : 0) * Kp + lr;
+        const float *row = DT + (size_t)kq * Kp + lr;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) an[b] = f < d ? row[(wave + kOmpWaves * b) * 16] : 0.f;
+        for (int b = 0; b < NB; ++b) an[b] = row[(wave + kOmpWaves * b) * 16];
     }
     for (int k0 = 0; k0 < dk; k0 += 4) {
         float a[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) a[b] = an[b];
         {
-            const int f = k0 + 4 + kq;
-            const float *row = DT + (size_t)(f < d ? f : 0) * Kp + lr;
+            const float *row = DT + (size_t)(k0 + 4 + kq) * Kp + lr;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) an[b] = f < d ? row[(wave + kOmpWaves * b) * 16] : 0.f;
+            for (int b = 0; b < NB; ++b) an[b] = row[(wave + kOmpWaves * b) * 16];
         }
         const int f = k0 + kq;
         float bx[CB];
@@ -299,7 +299,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         return;
     }
     const float xx = wave_sum(xv * xv);
-    const float xnorm = sqrtf(xx);
+    const float xnorm = __builtin_amdgcn_sqrtf(xx);
     const float eps_abs = p.relative ? p.eps * xnorm : p.eps;
     const float eps2 = eps_abs * eps_abs;
     const float band = 1e-5f * xx;     // FP32 uncertainty of the tracked ||r||^2
@@ -313,14 +313,14 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 
     // Key bit 31 marks an atom still selectable: any such key beats every
     // retired or padding atom, whatever their magnitude bits.
+    // alpha0 of the padding atoms (j >= K) is zero (their dictionary columns are)
     float a0[E];
     uint32_t kid[E];
+    load_row<E>(A0 + s * a0_stride(Kp) + lane * E, a0);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int j = lane * E + e;
-        const bool real = j < K;
-        a0[e] = real ? A0[s * a0_stride(Kp) + j] : 0.f;
-        kid[e] = (real ? kKeyLive : 0u) | (kKeyIdx - (uint32_t)j);
+        kid[e] = (j < K ? kKeyLive : 0u) | (kKeyIdx - (uint32_t)j);
     }
     float Lrow[KMAX], Lcol[KMAX];   // lane t: L[t][u] (u < t) and L[u][t] (u > t)
 #pragma unroll

@@ -97,7 +97,7 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
     h->device = dev;
     const int Kp = 64 * E;
     bool ok = hipMalloc(&h->D, sizeof(float) * (size_t)K * d) == hipSuccess &&
-              hipMalloc(&h->DT, sizeof(float) * (size_t)d * Kp) == hipSuccess &&
+              hipMalloc(&h->DT, sizeof(float) * (size_t)sc::dt_rows(d) * Kp) == hipSuccess &&
               hipMalloc(&h->G, sizeof(float) * (size_t)K * Kp) == hipSuccess &&
               hipMalloc(&h->Dbf, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->Dlo, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
@@ -128,7 +128,8 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
         free_dict(h);
         return SC_ENORM;
     }
-    if ((e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->D48, st)) != hipSuccess ||
+    if ((e = hipMemsetAsync(h->DT, 0, sizeof(float) * (size_t)sc::dt_rows(d) * Kp, st)) != hipSuccess ||
+        (e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->D48, st)) != hipSuccess ||
         (e = sc::launch_gram(h->D, d, K, Kp, h->G, h->G64, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         free_dict(h);

@@ -26,10 +26,14 @@ inline int pick_kmax(int k) {
     return -1;
 }
 
+// Rows of the feature-major dictionary DT: d rounded up to 4, plus one
+// further k-step of 4 zero rows (the correlation stage reads a k-step ahead).
+inline int dt_rows(int d) { return ((d + 3) & ~3) + 4; }
+
 struct DictDev {
     int d, K, Kp, E;
     const float *D;    // K x d atom-major FP32
-    const float *DT;   // d x Kp feature-major FP32, zero padded atoms
+    const float *DT;   // dt_rows(d) x Kp feature-major FP32, zero padded atoms and rows >= d
     const float *G;    // K x Kp FP32 Gram rows, zero padded columns
     const uint16_t *Dbf;  // Kp x 64 BF16 atom-major, features and atoms zero padded
     const uint16_t *Dlo;  // Kp x 64 BF16 residual D - bf16(D) (split-BF16 products)
