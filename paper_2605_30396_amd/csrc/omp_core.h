@@ -280,7 +280,12 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     constexpr int Kp = 64 * E;
     constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
     constexpr int kRowBatch = RCQ > 0 ? 1 : (KMAX >= 16 ? 2 : 3);   // within 128 VGPRs (4 waves per SIMD)
-    const int d = dict.d, K = dict.K, k = p.k;
+    const int d = dict.d, K = dict.K;
+    // k is re-read as an opaque scalar per signal, so the per-step tests
+    // against it are made where they are used rather than hoisted out of the
+    // signal loop (twelve hoisted masks would be spilled)
+    int k = p.k;
+    asm volatile("" : "+s"(k));
     const float *__restrict__ G = dict.G;
     const float *__restrict__ Dg = dict.D;
     const float xv = lane < d ? Xt[lane * xt_stride(T) + s] : 0.f;
@@ -338,9 +343,9 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     int n = 0, n_gam = 0;   // gamma is current for n_gam atoms
     bool active = xx > 0.f, expl_done = false;
 
-    // gamma = L^-T c for the first nn atoms.  Lane t's accumulator stops
-    // changing once step t is passed (column t of L is zero above the
-    // diagonal), so every lane forms its own gamma_t at the end.
+    // gamma = L^-T c for the first nn atoms: gamma_t is read from lane t as
+    // soon as its accumulator holds the terms of the later steps, and written
+    // back into lane t, so the entries of L above the diagonal are never used.
     auto back_sub = [&](int nn) {
         float acc = 0.f;
 #pragma unroll
@@ -348,9 +353,9 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             if (t < nn) {
                 const float gt = readlane_f((cval - acc) * linv, t);
                 acc = fmaf(Lcol[t], gt, acc);
+                gam = writelane_f(gt, t, gam);   // lane t: gamma_t
             }
         }
-        gam = (cval - acc) * linv;
         n_gam = nn;
     };
     // ||x - D_I gamma||^2 with the current gamma (lane i < d holds x_i)
@@ -503,6 +508,28 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             active = false;
             continue;
         }
+        // A selected atom keeps its live bit: its correlation with the
+        // residual is zero up to rounding, so it wins only when every live
+        // atom's correlation is as small.  Then the choice is made again with
+        // every selected atom masked (rare), which equals masking them all
+        // along; the per-lane key words stay unchanged.
+        if (it > 0 && (ballot(selv == (int)(kKeyIdx - (kb & kKeyIdx))) & ((1ull << it) - 1ull)) != 0) {
+            uint32_t dead = 0u;   // bit e: this lane's atom e is selected
+#pragma unroll
+            for (int t = 0; t < it; ++t) {
+                const int st = readlane_i(selv, t);
+                dead |= st / E == lane ? 1u << (st % E) : 0u;
+            }
+            best = 0u;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                best = max(best, ((dead >> e) & 1u) ? 0u : (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
+            kb = wave_max_u32(best);
+            if (!(__uint_as_float(kb & kKeyMag) > brk) || !(kb & kKeyLive)) {
+                active = false;
+                continue;
+            }
+        }
         const uint32_t kbi = kb & kKeyIdx;
         const int j = (int)(kKeyIdx - kbi);
         if (it < RC)
@@ -512,17 +539,18 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         // ---- new row of the Cholesky factor: L w = G[I, j] ----
         const float g = G[(size_t)selv * Kp + j];   // lanes >= it read an unused entry of row 0
         const float gjj = G[(size_t)j * Kp + j];
-        float acc = 0.f, wsq = 0.f, wc = 0.f;
+        // w_t is read from lane t once its accumulator holds the earlier
+        // terms; lane t keeps w_t (wv) and lane `it` the new row of L
+        float acc = 0.f, wsq = 0.f, wc = 0.f, wv = 0.f;
 #pragma unroll
         for (int t = 0; t < it; ++t) {
             const float wt = readlane_f((g - acc) * linv, t);
             acc = fmaf(Lrow[t], wt, acc);
             wsq = fmaf(wt, wt, wsq);
             wc = fmaf(wt, readlane_f(cval, t), wc);
-            Lrow[t] = lane == it ? wt : Lrow[t];
+            Lrow[t] = writelane_f(wt, it, Lrow[t]);
+            wv = writelane_f(wt, t, wv);
         }
-        // lane t < it holds w_t (its accumulator is final once step t is passed)
-        const float wv = lane < it ? (g - acc) * linv : 0.f;
         const float l2 = gjj - wsq;
         if (!(l2 > 1e-9f * gjj)) {   // numerically dependent on the selected atoms
             active = false;
@@ -540,22 +568,16 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         lmax = fmaxf(lmax, ell);
         lmin = fminf(lmin, ell);
         Lcol[it] = wv;
-        cval = lane == it ? cn : cval;
-        linv = lane == it ? inv : linv;
-        selv = lane == it ? j : selv;
-        // retire atom j from the selection
-#pragma unroll
-        for (int e = 0; e < E; ++e) kid[e] = kid[e] == (kKeyLive | kbi) ? kbi : kid[e];
+        cval = writelane_f(readfirstlane_f(cn), it, cval);
+        linv = writelane_f(readfirstlane_f(inv), it, linv);
+        selv = writelane_i(j, it, selv);
         n = it + 1;
     }
 
     // ---- coefficients, residual, outputs ----
     if (__builtin_amdgcn_readfirstlane(n_gam) != n) back_sub(n);
     bool refit = false;
-    if (n > 0 && p.fp64_refit) {
-        const float q = lmax / lmin;
-        refit = q * q > p.kappa_max;
-    }
+    if (n > 0 && p.fp64_refit) refit = lmax * lmax > p.kappa_max * (lmin * lmin);
     float re = 0.f;
     if (!refit) re = expl_done ? rr_expl : resid2(n);
     if (lane < k) {
@@ -564,7 +586,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     }
     if (lane == 0) {
         p.count[sig] = refit ? -(2 + n) : n;
-        if (p.resid) p.resid[sig] = refit ? 0.f : sqrtf(re);
+        if (p.resid) p.resid[sig] = refit ? 0.f : __builtin_amdgcn_sqrtf(re);
     }
     tally.sig += 1;
     tally.atoms += n;

@@ -22,6 +22,20 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
 
 __device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+// v with lane `lane` replaced by the wave-uniform x (v_writelane_b32: no exec
+// mask or lane compare needed).  x and lane must be wave-uniform: x is passed
+// in a scalar register and the lane in M0 (an instruction may read only one
+// SGPR besides M0).  The compiler has no builtin for this instruction, hence
+// the asm; it reads and writes registers only.
+__device__ __forceinline__ int writelane_i(int x, int lane, int v) {
+    x = __builtin_amdgcn_readfirstlane(x);   // free when x is already scalar
+    asm("v_writelane_b32 %0, %1, m0" : "+v"(v) : "s"(x), "{m0}"(lane));
+    return v;
+}
+__device__ __forceinline__ float writelane_f(float x, int lane, float v) {
+    return __int_as_float(writelane_i(__float_as_int(x), lane, __float_as_int(v)));
+}
+
 // Lane 0's value, known to the compiler as wave-uniform (callers pass values
 // that are equal on every lane, so branches on them need no exec masking).
 __device__ __forceinline__ float readfirstlane_f(float v) {
