@@ -81,6 +81,141 @@ def read_traffic(kernel, src_hash):
         return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_errors(D, X, k, eps, gpu, sample, threads):
+    """Codes of the seeded subsample `sample` against the FP64 oracle's:
+    aggregate residual gap (negative = below the oracle's greedy path), the
+    99th percentile and maximum of |r_gpu - r_oracle| / ||x|| per signal,
+    and the share of signals with another support."""
+    import oracle
+    ref = oracle.omp(D, X[sample], k, eps, nthreads=threads)
+    gi, gr = gpu[0], gpu[3].astype(np.float64)
+    rr = ref["resid"]
+    xn = np.linalg.norm(X[sample].astype(np.float64), axis=1)
+    agg = np.sqrt((rr ** 2).sum())
+    dev = np.abs(gr - rr) / np.maximum(xn, 1e-30)
+    return {"sample": int(len(sample)), "resid_gap": float((np.sqrt((gr ** 2).sum()) - agg) / agg),
+            "resid_dev_p99": float(np.quantile(dev, 0.99)), "resid_dev_max": float(dev.max()),
+            "support_mismatch": float(np.mean(np.any(gi != ref["idx"], axis=1)))}
+
+
+def other_workloads(args, log, sc, I, autotune, torch, dev, stream, ev):
+    """The SH-like and precision-form workloads, each timed as a step on its
+    own (inputs resident), with roofline fractions and errors against the FP64
+    oracle on a seeded subsample."""
+    threads = len(os.sched_getaffinity(0))
+    rng = np.random.Generator(np.random.PCG64(12))
+    out = {}
+
+    def time_steps(fn, nmarks):
+        for _ in range(args.warmup):
+            fn([ev() for _ in range(nmarks)])
+        torch.cuda.synchronize()
+        rec = []
+        for _ in range(args.steps):
+            m = [ev() for _ in range(nmarks)]
+            fn(m)
+            rec.append(m)
+        torch.cuda.synchronize()
+        return [float(np.mean([m[i].elapsed_time(m[i + 1]) for m in rec])) for i in range(nmarks - 1)]
+
+    # SH-like coefficients, K = 256 dictionary learned by MOD, k = 8, eps = 1e-3, one view per Gaussian
+    t0 = time.perf_counter()
+    w = I.workload_sh_like(N=1_000_000)
+    D2 = np.load(os.path.join(ROOT, "tests", "golden", "sh_like_dict_K256.npy"))
+    X2 = torch.from_numpy(w["X"]).to(dev)
+    dir2 = torch.from_numpy(w["dirs"]).to(dev)
+    N2, k2, e2 = X2.shape[0], w["k"], w["eps"]
+    h2 = sc.gram_precompute(torch.from_numpy(D2).to(dev))
+    tune2 = autotune.tune_dictionary(h2, X2, k2, e2, use_cache=False)
+    o2 = sc.omp_encode(h2, X2, k2, e2)
+    rgb2 = torch.empty((N2, 3), dtype=torch.float32, device=dev)
+
+    def step2(m):
+        m[0].record(stream)
+        sc.omp_encode(h2, X2, k2, e2, out=o2)
+        m[1].record(stream)
+        sc.sh_eval_sparse(h2, o2[0], o2[1], o2[2], dir2, sc.DIRS_PER_SIGNAL, out=rgb2)
+        m[2].record(stream)
+    sc.omp_stats(h2, reset=True)
+    ph = time_steps(step2, 3)
+    st = sc.omp_stats(h2)
+    cnt = o2[2].cpu().numpy()
+    codes = [t.cpu().numpy() for t in o2]
+    sample = np.sort(rng.choice(N2, min(args.oracle_sample, N2), replace=False))
+    err = oracle_errors(D2, w["X"], k2, e2, [c[sample] for c in codes], sample, threads)
+    fl = batch_omp_flops(D2.shape[0], 45, cnt)
+    nnz = float(np.maximum(cnt, 0).sum())
+    rad_bytes = 8.0 * nnz + 28.0 * N2
+    out["sh_like_K256_k8"] = {
+        "workload": "1e6 SH-like rest vectors (Laplace 0.3*2^-l per band, RGB rho=0.8), K=256 MOD dictionary, "
+                    "k=8, eps=1e-3, FP32; step = encode + one-view radiance",
+        "N": N2, "ms_per_step": round(ph[0] + ph[1], 4), "ms_encode": round(ph[0], 4), "ms_radiance": round(ph[1], 4),
+        "gaussians_per_s": round(N2 / ((ph[0] + ph[1]) * 1e-3), 1), "mean_atoms": round(nnz / N2, 4),
+        "encode_roofline": {"bound": "alu", "achieved": round(fl / (ph[0] * 1e-3) / 1e12, 3),
+                            "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(fl / (ph[0] * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)},
+        "radiance_roofline": {"bound": "hbm", "achieved": round(rad_bytes / (ph[1] * 1e-3) / 1e9, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(rad_bytes / (ph[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "bytes_per_gaussian": "8 per non-zero + 28"},
+        "fp64_refit_rate": st["fp64_refits"] / (N2 * (args.steps + args.warmup)),
+        "vs_oracle": err, "encoder_tuning": tune2}
+    log(f"SH-like workload {ph} ms, error {err} ({time.perf_counter() - t0:.1f} s)")
+    h2.destroy()
+    del X2, dir2, o2, rgb2
+
+    # precision form: K = 512, k = 12, eps = 0, 5% near-duplicate signals; FP32 and split-BF16 correlations
+    t0 = time.perf_counter()
+    w = I.workload_precision(N=3_000_000)
+    D3 = w["D"]
+    X3 = torch.from_numpy(w["X"]).to(dev)
+    N3, k3 = X3.shape[0], w["k"]
+    h3 = sc.gram_precompute(torch.from_numpy(D3).to(dev))
+    tune3 = autotune.tune_dictionary(h3, X3, k3, 0.0, use_cache=False)
+    tune3["row_cache_bf16"] = autotune.tune_dictionary(h3, X3, k3, 0.0, sc.PREC_BF16, use_cache=False)["row_cache_bf16"]
+    o3 = sc.omp_encode(h3, X3, k3, 0.0)
+    sample = np.sort(rng.choice(N3, min(args.oracle_sample, N3), replace=False))
+    rows = {}
+    for name, flags in (("fp32", 0), ("bf16_precision_form", sc.PREC_BF16)):
+        def step3(m, flags=flags):
+            m[0].record(stream)
+            sc.omp_encode(h3, X3, k3, 0.0, flags, out=o3)
+            m[1].record(stream)
+        sc.omp_stats(h3, reset=True)
+        ph = time_steps(step3, 2)
+        st = sc.omp_stats(h3)
+        codes = [t.cpu().numpy() for t in o3]
+        cnt = codes[2]
+        fl = batch_omp_flops(D3.shape[0], 45, cnt)
+        rows[name] = {"ms": round(ph[0], 4), "gaussians_per_s": round(N3 / (ph[0] * 1e-3), 1),
+                      "roofline": {"bound": "alu", "achieved": round(fl / (ph[0] * 1e-3) / 1e12, 3),
+                                   "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(fl / (ph[0] * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS, 4)},
+                      "fp64_refit_rate": st["fp64_refits"] / (N3 * (args.steps + args.warmup)),
+                      "vs_oracle": oracle_errors(D3, w["X"], k3, 0.0, [c[sample] for c in codes], sample, threads)}
+        log(f"precision workload {name}: {ph[0]:.2f} ms, {rows[name]['vs_oracle']}")
+    out["precision_K512_k12_neardup"] = {
+        "workload": "3e6 signals, 4-sparse over a K=512 Gaussian unit-norm dictionary + N(0,sigma=1e-3) noise, "
+                    "5% near-duplicate rows (copies + N(0,1e-4^2)), k=12, eps=0",
+        "N": N3, "encoder_tuning": tune3, **rows}
+    log(f"precision workload done in {time.perf_counter() - t0:.1f} s")
+    h3.destroy()
+    del X3, o3
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +228,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6_000_000)
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-scene batched comparator")
     ap.add_argument("--no-sweep", action="store_true", help="skip the tolerance / CSC storage sweep")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the SH-like (1M, K=256) and precision-form (3M, K=512) workload lines")
+    ap.add_argument("--oracle-sample", type=int, default=200_000,
+                    help="seeded subsample of those workloads checked against the FP64 oracle")
     ap.add_argument("--proposer-weights", default=None,
                     help="FP32 parameter file (.npy): loaded instead of training when it exists, else written "
                          "after training (lets counter passes reuse the proposer a traced run trained)")
@@ -141,6 +280,7 @@ def main():
         cpu_ref = oracle.omp(D, X[:ns], k, eps, nthreads=threads)
         dtc = time.perf_counter() - tc
         cpu = {"value": round(ns / dtc, 1), "unit": "Gaussians/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
                "sample": f"first {ns} of the {N} signals, FP64 OMP (Householder-QR least squares), "
                          f"{threads} threads, {dtc:.1f} s"}
         log(f"CPU oracle baseline: {cpu['value']:.0f} Gaussians/s on {threads} threads")
@@ -176,6 +316,7 @@ def main():
     else:
         sup, cnt = trainer.omp_labels(h, Xtr_g, k, eps)
         hist = trainer.train(prop, Xtr_g, sup, cnt, epochs=args.epochs, batch=1024, lr=3e-3, pos_weight=8.0, seed=1)
+        hist["recall_train"] = trainer.support_recall(prop, Xtr_g[:20000], sup[:20000], cnt[:20000])
         del sup, cnt
         if args.proposer_weights:
             np.save(args.proposer_weights, prop.get_params().cpu().numpy())
@@ -320,6 +461,14 @@ def main():
     recall_screen = float(np.mean([set(li[i, :max(lc[i], 0)]) <= set(scr[i]) for i in range(len(scr))]))
     for v in results.values():
         v["gaussians_per_s"] = round(N / (v["ms"] * 1e-3), 1)
+
+    # ---- the other single-GPU workloads: SH-like (1M, K=256, k=8) and the
+    # precision form (3M, K=512, k=12, eps=0, 5% near-duplicates) ----
+    workloads = None
+    if not args.no_workloads:
+        del cand, miss_rows
+        torch.cuda.empty_cache()
+        workloads = other_workloads(args, log, sc, I, autotune, torch, dev, stream, ev)
 
     # ---- the 16-scene batch in one persistent launch ----
     batched = None
@@ -466,11 +615,13 @@ def main():
         "speedup_vs_plain_fp32": (round(plain["ms"] / results["learned_bf16_proposer"]["ms"], 4) if plain else None),
         "comparators": {k2: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k2, v in results.items()},
+        "workloads": workloads,
         "batched": batched,
         "tolerance_sweep": sweep,
         "kernels": per_kernel,
         "training": {"seconds": round(train_s, 2), "epochs": args.epochs, "train_N": args.train_N,
                      "final_loss": round(hist["loss"][-1], 5), "recall_at_24": recall,
+                     "recall_at_24_train": hist.get("recall_train"),
                      "recall_at_24_untrained": recall0, "recall_at_24_screening": recall_screen},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -120,18 +120,16 @@ int sc_dict_gram(sc_dict h, float *G_out, void *stream);
  * coefficients from D_I^T x.
  *
  * Precision (flags): FP32 throughout by default.  SC_PREC_BF16 forms
- * alpha0 = D^T x on BF16 MFMA with FP32 accumulation as a split product,
- * D = Dh + Dl and x = xh + xl in BF16, alpha0 = Dh xh + Dl xh + Dh xl (error
- * <= 1.6e-5 ||x|| per unit atom); the correlations are then updated in Gram
- * form in FP32 as in the default path.  Before each selection, every atom
- * whose |correlation| lies within twice that error bound of the best one is
- * re-correlated in FP32 from x (its alpha0 replaced by the exact value), so
- * the selections are those of the FP32 correlations and the chosen atom's
- * alpha0, which the coefficients, the tracked residual and the stop test
- * use, is FP32.  The Cholesky factor, the stop test and the final
- * coefficients stay FP32.  Supports whose Cholesky condition estimate
- * (max l_ii / min l_ii)^2 exceeds 1e3 are refit in FP64 unless
- * SC_NO_FP64_REFIT.
+ * alpha0 = D^T x on BF16 matrix cores with FP32 accumulation: D and x are
+ * each split into three BF16 parts (every part the rounding of what the
+ * previous ones leave) and the six products of scale >= 2^-16 are summed in
+ * FP32 (Dm xm + Dl xh + Dh xl + Dm xh + Dh xm + Dh xh).  The products left
+ * out and the parts' own rounding add <= 4 * 2^-27 ||x|| per unit atom, so
+ * the correlations have the accuracy of FP32 dot products, at half the
+ * matrix-core time of FP32 operands.  The Gram-form update, the Cholesky
+ * factor, the stop test and the coefficients are FP32 as in the default
+ * path.  Supports whose Cholesky condition estimate (max l_ii / min l_ii)^2
+ * exceeds 1e3 are refit in FP64 unless SC_NO_FP64_REFIT.
  *
  *   X      device N x d float32          idx   device N x k int32 (out)
  *   N      >= 0 (0: no device work, the  coef  device N x k float32 (out)

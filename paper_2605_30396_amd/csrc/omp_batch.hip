@@ -5,11 +5,10 @@
 // alpha0 modes:
 //   A0_VALU         FP32 FMAs from the feature-major dictionary
 //   A0_MFMA_F32     v_mfma_f32_16x16x4_f32, FP32 operands (same precision)
-//   A0_MFMA_BF16X3  v_mfma_f32_16x16x32_bf16 on the split D = Dh + Dl,
-//                   x = xh + xl: Dh xh + Dl xh + Dh xl, relative error ~2^-16.
-//                   Only the selection sees this error: alpha0_j of each
-//                   selected atom is recomputed in FP32, so coefficients,
-//                   tracked residual and stop test are FP32 throughout.
+//   A0_MFMA_BF16X6  v_mfma_f32_16x16x32_bf16 on three-part BF16 splits of D
+//                   and x, six products summed in FP32: correlations of FP32
+//                   accuracy from BF16 matrix cores (half the matrix-core time
+//                   of A0_MFMA_F32).
 #include <algorithm>
 
 #include "omp_batch_impl.h"
@@ -38,7 +37,7 @@ hipError_t launch_omp_batch(const DictDev &dict, const OmpParams &p, int kmax, i
     switch (a0mode) {
         case A0_VALU: return launch_omp_batch_valu(dict, p, kmax, row_cache, st);
         case A0_MFMA_F32: return launch_omp_batch_mfma(dict, p, kmax, row_cache, st);
-        case A0_MFMA_BF16X3: return launch_omp_batch_bf16(dict, p, kmax, row_cache, st);
+        case A0_MFMA_BF16X6: return launch_omp_batch_bf16(dict, p, kmax, row_cache, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kOmpThreads) void omp_batch_kernel(DictDev dict, Om
         // live across the loop
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        omp_tile<E, KMAX, kTileS, MODE == A0_MFMA_BF16X3, RCQ>(dict, p, MODE, s0, nt, smem_raw, tid, tally);
+        omp_tile<E, KMAX, kTileS, MODE == A0_MFMA_BF16X6, RCQ>(dict, p, MODE, s0, nt, smem_raw, tid, tally);
     }
     // counters: one pair of atomics per workgroup (device-wide atomics on one
     // address serialise, and every wave ends at about the same time)
@@ -58,7 +58,7 @@ inline int device_cus() {
 template <int E, int KMAX, int MODE, int RCQ>
 static hipError_t launch_batch_t(const DictDev &dict, const OmpParams &p, hipStream_t st) {
     constexpr int Kp = 64 * E;
-    const size_t smem = omp_tile_lds(kTileS, Kp, MODE == A0_MFMA_BF16X3);
+    const size_t smem = omp_tile_lds(kTileS, Kp, MODE == A0_MFMA_BF16X6);
     auto kern = omp_batch_kernel<E, KMAX, MODE, RCQ>;
     static bool attr_set = false;
     if (!attr_set) {

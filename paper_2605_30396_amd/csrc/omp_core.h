@@ -54,19 +54,19 @@ __host__ __device__ constexpr int a0_stride(int Kp) { return Kp + 4; }
 // bytes aligned for the vector reads of the VALU correlation.
 __host__ __device__ constexpr int xt_stride(int T) { return T + 4; }
 
-// The two BF16 signal parts [T][kXhs] of the split-BF16 correlations live
+// The three BF16 signal parts [T][kXhs] of the split-BF16 correlations live
 // inside the alpha0 tile when it is large enough: they are read only before
 // the tile is written.
 __host__ __device__ constexpr bool split_in_a0(int T, int Kp) {
-    return 2 * T * kXhs * (int)sizeof(uint16_t) <= T * a0_stride(Kp) * (int)sizeof(float);
+    return 3 * T * kXhs * (int)sizeof(uint16_t) <= T * a0_stride(Kp) * (int)sizeof(float);
 }
 
 // LDS bytes of one workgroup: alpha0 tile [T][a0_stride(Kp)], signal tile
-// [64][xt_stride(T)], and for the split-BF16 correlations the two BF16
+// [64][xt_stride(T)], and for the split-BF16 correlations the three BF16
 // signal parts when they do not fit inside the alpha0 tile.
 __host__ __device__ constexpr size_t omp_tile_lds(int T, int Kp, bool split) {
     return sizeof(float) * ((size_t)T * a0_stride(Kp) + 64 * (size_t)xt_stride(T)) +
-           (split && !split_in_a0(T, Kp) ? sizeof(uint16_t) * 2 * T * kXhs : 0);
+           (split && !split_in_a0(T, Kp) ? sizeof(uint16_t) * 3 * T * kXhs : 0);
 }
 
 struct OmpTally {
@@ -210,13 +210,21 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ DT, in
                 acc[b][c];
 }
 
-// alpha0 tile (16 signals) as the split BF16 product Dh xh + Dl xh + Dh xl,
-// features padded to 64 (v_mfma_f32_16x16x32_bf16); relative error ~2^-16.
+// alpha0 tile (16 signals) from BF16 matrix cores at FP32 accuracy: D and x
+// are each split into three BF16 parts (v = vh + vm + vl, every part the
+// rounding of what the previous ones leave), and the six products whose
+// scale is at least 2^-16 are summed in FP32, smallest first:
+//   Dm xm + Dl xh + Dh xl + Dm xh + Dh xm + Dh xh.
+// The products left out (Dm xl, Dl xm, Dl xl) and the parts' own rounding
+// are each <= 2^-27 |a_i x_i|, so they add <= 4 2^-27 ||x|| for a unit atom;
+// the FP32 accumulation error is that of an FP32 dot product.  Features are
+// padded to 64 (v_mfma_f32_16x16x32_bf16).
 template <int E>
-__device__ __forceinline__ void alpha0_mfma_bf16x3(const uint16_t *__restrict__ Dh, const uint16_t *__restrict__ Dl,
-                                                   const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xl,
+__device__ __forceinline__ void alpha0_mfma_bf16x6(const uint16_t *__restrict__ Dh, const uint16_t *__restrict__ Dm,
+                                                   const uint16_t *__restrict__ Dl, const uint16_t *__restrict__ Xh,
                                                    float *__restrict__ A0, int wave, int lane) {
     constexpr int Kp = 64 * E, MT = Kp / 16, NB = MT / kOmpWaves;
+    const uint16_t *Xm = Xh + 16 * kXhs, *Xl = Xm + 16 * kXhs;
     const int lr = lane & 15, kq = lane >> 4;
     floatx4 acc[NB];
 #pragma unroll
@@ -224,18 +232,23 @@ __device__ __forceinline__ void alpha0_mfma_bf16x3(const uint16_t *__restrict__ 
 #pragma unroll
     for (int k0 = 0; k0 < 64; k0 += 32) {
         const bf16x8 bh = ld_bf16x8(Xh + lr * kXhs + k0 + 8 * kq);
+        const bf16x8 bm = ld_bf16x8(Xm + lr * kXhs + k0 + 8 * kq);
         const bf16x8 bl = ld_bf16x8(Xl + lr * kXhs + k0 + 8 * kq);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int atom = (wave + kOmpWaves * b) * 16 + lr;
-            const bf16x8 ah = ld_bf16x8(Dh + (size_t)atom * 64 + k0 + 8 * kq);
-            const bf16x8 al = ld_bf16x8(Dl + (size_t)atom * 64 + k0 + 8 * kq);
+            const size_t off = (size_t)((wave + kOmpWaves * b) * 16 + lr) * 64 + k0 + 8 * kq;
+            const bf16x8 ah = ld_bf16x8(Dh + off);
+            const bf16x8 am = ld_bf16x8(Dm + off);
+            const bf16x8 al = ld_bf16x8(Dl + off);
+            acc[b] = mfma16(am, bm, acc[b]);
             acc[b] = mfma16(al, bh, acc[b]);
             acc[b] = mfma16(ah, bl, acc[b]);
+            acc[b] = mfma16(am, bh, acc[b]);
+            acc[b] = mfma16(ah, bm, acc[b]);
             acc[b] = mfma16(ah, bh, acc[b]);
         }
     }
-    __syncthreads();   // every wave has read Xh and Xl, which may share the alpha0 tile
+    __syncthreads();   // every wave has read the signal parts, which may share the alpha0 tile
 #pragma unroll
     for (int b = 0; b < NB; ++b)
         *reinterpret_cast<floatx4 *>(A0 + lr * a0_stride(Kp) + (wave + kOmpWaves * b) * 16 + 4 * kq) = acc[b];
@@ -263,17 +276,12 @@ __device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)
     }
 }
 
-// Encodes signal `sig` (column s of the tile) with one wave.  kSplit: alpha0
-// holds the split-BF16 correlations; before each selection, every atom that
-// could still beat the best one within the split-BF16 error bound is
-// re-correlated in FP32 from the signal, so the selections are those of the
-// FP32 correlations, and the chosen atom's alpha0 (which the coefficients,
-// the tracked residual and the stop test use) is exact FP32.
+// Encodes signal `sig` (column s of the tile) with one wave.
 // RCQ: the Gram rows of the atoms of the first RCQ steps are kept in
 // registers (RCQ * E VGPRs).  The row of the newest atom is fetched as soon
 // as the atom is chosen and held for the next step; older rows are re-read
 // kRowBatch at a time whenever alpha is formed.
-template <int E, int KMAX, bool kSplit, int T, int RCQ>
+template <int E, int KMAX, int T, int RCQ>
 __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams &p, int64_t sig, int s,
                                             const float *__restrict__ Xt, const float *__restrict__ A0, int lane,
                                             OmpTally &tally) {
@@ -309,12 +317,6 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     const float eps2 = eps_abs * eps_abs;
     const float band = 1e-5f * xx;     // FP32 uncertainty of the tracked ||r||^2
     const float brk = 1e-6f * xnorm;   // residual orthogonal to every atom
-    // Bound on the error of a split-BF16 alpha0 entry (unit atom): the terms
-    // the three products leave out are each <= 2^-18 |a_i x_i|, so <= 3 2^-18
-    // ||x|| in all (Cauchy-Schwarz), plus FP32 accumulation of 64 products
-    // (<= 64 2^-24 ||x||): 1.52e-5 ||x||.
-    const float split_err = 1.6e-5f * xnorm;
-    uint32_t exact = 0u;               // bit e: a0[e] is the FP32 correlation
 
     // Key bit 31 marks an atom still selectable: any such key beats every
     // retired or padding atom, whatever their magnitude bits.
@@ -455,55 +457,6 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 #pragma unroll
         for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
         uint32_t kb = wave_max_u32(best);
-        if constexpr (kSplit) {
-            // An atom whose split-BF16 alpha0 is not yet exact may be off by
-            // up to split_err.  When another atom besides the best lies within
-            // 2 split_err of it, every such atom that is not exact is
-            // re-correlated in FP32 (alpha0 and alpha take the exact value)
-            // and the best is found again; an atom left out is then below the
-            // best by more than its error, so the choice is the one the FP32
-            // correlations give.  (The best atom itself needs no repair when
-            // it is alone: its alpha0 is recomputed in FP32 below.)
-            for (;;) {
-                const float thr = __uint_as_float(kb & kKeyMag) - 2.f * split_err;
-                uint32_t cm = 0u;
-                int near = 0;
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const bool in = (kid[e] & kKeyLive) && fabsf(al[e]) >= thr;
-                    near += in ? 1 : 0;
-                    cm |= (in && !((exact >> e) & 1u)) ? (1u << e) : 0u;
-                }
-                const uint64_t one = ballot(near >= 1);
-                if (ballot(near >= 2) == 0 && __popcll(one) <= 1) break;   // the best is alone
-                uint64_t lanes = ballot(cm != 0u);
-                if (lanes == 0) break;   // everything in contention is exact already
-                while (lanes) {
-                    const int l = __ffsll((unsigned long long)lanes) - 1;
-                    lanes &= lanes - 1;
-                    uint32_t cl = (uint32_t)__builtin_amdgcn_readlane((int)cm, l);
-                    while (cl) {
-                        const int e = __ffs(cl) - 1;
-                        cl &= cl - 1;
-                        const float z = wave_sum(lane < d ? Dg[(size_t)(l * E + e) * d + dl] * xv : 0.f);
-                        if (lane == l) {
-#pragma unroll
-                            for (int q = 0; q < E; ++q) {
-                                if (q == e) {
-                                    al[q] += z - a0[q];
-                                    a0[q] = z;
-                                }
-                            }
-                            exact |= 1u << e;
-                        }
-                    }
-                }
-                best = 0u;
-#pragma unroll
-                for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
-                kb = wave_max_u32(best);
-            }
-        }
         if (!(__uint_as_float(kb & kKeyMag) > brk)) {
             active = false;
             continue;
@@ -558,11 +511,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         }
         const float ell = __builtin_amdgcn_sqrtf(l2);
         const float inv = __builtin_amdgcn_rcpf(ell);
-        float zj;
-        if constexpr (kSplit)   // the chosen atom's alpha0 in FP32
-            zj = wave_sum(lane < d ? Dg[(size_t)j * d + lane] * xv : 0.f);
-        else
-            zj = A0[s * a0_stride(Kp) + j];
+        const float zj = A0[s * a0_stride(Kp) + j];
         const float cn = (zj - wc) * inv;
         rr = readfirstlane_f(fmaf(-cn, cn, rr));
         lmax = fmaxf(lmax, ell);
@@ -593,7 +542,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 }
 
 // One tile of T signals: load, alpha0 by `mode` (A0_VALU or A0_MFMA_F32; or
-// A0_MFMA_BF16X3 when kSplitOK, T == 16 and the LDS holds the split parts),
+// A0_MFMA_BF16X6 when kSplitOK, T == 16 and the LDS holds the split parts),
 // then each wave encodes its signals.
 template <int E, int KMAX, int T, bool kSplitOK, int RCQ>
 __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p, int mode, int64_t s0, int nt,
@@ -606,25 +555,27 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
     __syncthreads();   // the previous tile is done with Xt and A0
     load_tile<T>(p, dict.d, s0, nt, Xt, tid);
     __syncthreads();
-    bool split = false, done = false;
+    bool done = false;
     if constexpr (T % 16 == 0) {   // the MFMA stages work on 16-signal column blocks
         if (mode == A0_MFMA_F32) {
             alpha0_mfma_f32<E, T>(dict.DT, dict.d, Xt, A0, wave, lane);
             done = true;
-        } else if (kSplitOK && T == 16 && mode == A0_MFMA_BF16X3) {
+        } else if (kSplitOK && T == 16 && mode == A0_MFMA_BF16X6) {
+            // signal parts [3][T][kXhs]: x = xh + xm + xl in BF16
             uint16_t *Xh = split_in_a0(T, Kp) ? reinterpret_cast<uint16_t *>(A0)
                                               : reinterpret_cast<uint16_t *>(Xt + 64 * xt_stride(T));
-            uint16_t *Xl = Xh + T * kXhs;
             for (int q = tid; q < T * 64; q += kOmpThreads) {
                 const int s = q >> 6, f = q & 63;
                 const float v = Xt[f * xt_stride(T) + s];
                 const uint16_t hi = bf16_bits(v);
+                const float r1 = v - bf16_to_f32(hi);
+                const uint16_t mid = bf16_bits(r1);
                 Xh[s * kXhs + f] = hi;
-                Xl[s * kXhs + f] = bf16_bits(v - bf16_to_f32(hi));
+                Xh[(T + s) * kXhs + f] = mid;
+                Xh[(2 * T + s) * kXhs + f] = bf16_bits(r1 - bf16_to_f32(mid));
             }
             __syncthreads();
-            alpha0_mfma_bf16x3<E>(dict.Dbf, dict.Dlo, Xh, Xl, A0, wave, lane);
-            split = true;
+            alpha0_mfma_bf16x6<E>(dict.Dbf, dict.Dlo, dict.Dl2, Xh, A0, wave, lane);
             done = true;
         }
     }
@@ -633,10 +584,7 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
     for (int s = wave; s < nt; s += kOmpWaves) {
         const int64_t sig = p.rows ? (int64_t)p.rows[s0 + s] : s0 + s;
         if (p.rows && (uint64_t)sig >= (uint64_t)p.N) continue;   // out-of-range list entry: skipped
-        if (kSplitOK && split)
-            omp_pursuit<E, KMAX, kSplitOK, T, RCQ>(dict, p, sig, s, Xt, A0, lane, tally);
-        else
-            omp_pursuit<E, KMAX, false, T, RCQ>(dict, p, sig, s, Xt, A0, lane, tally);
+        omp_pursuit<E, KMAX, T, RCQ>(dict, p, sig, s, Xt, A0, lane, tally);
     }
 }
 

@@ -52,6 +52,7 @@ void free_dict(sc_dict h) {
     hipFree(h->G);
     hipFree(h->Dbf);
     hipFree(h->Dlo);
+    hipFree(h->Dl2);
     hipFree(h->D48);
     hipFree(h->G64);
     hipFree(h->status);
@@ -101,6 +102,7 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
               hipMalloc(&h->G, sizeof(float) * (size_t)K * Kp) == hipSuccess &&
               hipMalloc(&h->Dbf, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->Dlo, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
+              hipMalloc(&h->Dl2, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->D48, sizeof(float) * (size_t)K * 48) == hipSuccess &&
               hipMalloc(&h->G64, sizeof(double) * (size_t)K * K) == hipSuccess &&
               hipMalloc(&h->status, sizeof(int) * 4) == hipSuccess &&
@@ -129,13 +131,13 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
         return SC_ENORM;
     }
     if ((e = hipMemsetAsync(h->DT, 0, sizeof(float) * (size_t)sc::dt_rows(d) * Kp, st)) != hipSuccess ||
-        (e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->D48, st)) != hipSuccess ||
+        (e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->Dl2, h->D48, st)) != hipSuccess ||
         (e = sc::launch_gram(h->D, d, K, Kp, h->G, h->G64, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         free_dict(h);
         return set_dev_error("sc_gram_precompute", e);
     }
-    h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->D48, h->G64};
+    h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->Dl2, h->D48, h->G64};
     h->row_cache = E <= 4 ? 4 : 0;
     h->row_cache_bf16 = h->row_cache;
     // device copy of the layout descriptor, read by the multi-scene encoder
@@ -184,7 +186,7 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
     sc::OmpParams p{X, N, nullptr, nullptr, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0,
                     (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, idx, coef, count, resid, h->stats};
     hipStream_t st = (hipStream_t)stream;
-    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
+    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X6 : h->a0_fp32;
     hipError_t e = sc::launch_omp_batch(h->dev, p, kmax, a0, row_cache_for(h, flags), st);
     if (e == hipErrorInvalidValue) {
         snprintf(g_last_error, sizeof(g_last_error), "no compiled encoder for K=%d (Kp=%d) with k=%d", K,
@@ -527,7 +529,7 @@ int sc_omp_encode_learned(sc_dict h, sc_proposer p, const float *X, int64_t N, i
     // the restricted pursuit never takes more than kcap steps: size its registers for that
     SC_HIP(sc::launch_omp_restricted(h->dev, h->D48, rp, sc::pick_kmax(kcap), st), "sc_omp_encode_learned (restricted)");
     sc::OmpParams fp{X, N, miss_rows, miss_count, k, eps, rel, refit, kKappaMax, idx, coef, count, resid, h->stats};
-    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
+    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X6 : h->a0_fp32;
     SC_HIP(sc::launch_omp_batch(h->dev, fp, kmax, a0, row_cache_for(h, flags), st), "sc_omp_encode_learned (fallback)");
     return SC_OK;
 }
@@ -627,7 +629,7 @@ int sc_omp_encode_rows(sc_dict h, const float *X, const int32_t *rows, const int
     if (!X || !rows || !nrows || !idx || !coef || !count) return SC_EINVAL;
     sc::OmpParams p{X, max_rows, rows, nrows, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0,
                     (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, idx, coef, count, resid, h->stats};
-    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X3 : h->a0_fp32;
+    const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X6 : h->a0_fp32;
     hipError_t e = sc::launch_omp_batch(h->dev, p, sc::pick_kmax(k), a0, row_cache_for(h, flags), (hipStream_t)stream);
     if (e == hipErrorInvalidValue) return SC_EINVAL;
     if (e != hipSuccess) return set_dev_error("sc_omp_encode_rows", e);

@@ -36,13 +36,14 @@ struct DictDev {
     const float *DT;   // dt_rows(d) x Kp feature-major FP32, zero padded atoms and rows >= d
     const float *G;    // K x Kp FP32 Gram rows, zero padded columns
     const uint16_t *Dbf;  // Kp x 64 BF16 atom-major, features and atoms zero padded
-    const uint16_t *Dlo;  // Kp x 64 BF16 residual D - bf16(D) (split-BF16 products)
+    const uint16_t *Dlo;  // Kp x 64 BF16 middle part bf16(D - Dbf) (split-BF16 products)
+    const uint16_t *Dl2;  // Kp x 64 BF16 low part bf16(D - Dbf - Dlo)
     const float *D48;     // K x 48 FP32 atom-major, features zero padded (d <= 48)
     const double *G64;    // K x K Gram, exact products summed in FP64 (not rounded)
 };
 
 // How the correlation tile alpha0 = D^T X is computed by the batch encoder.
-enum { A0_VALU = 0, A0_MFMA_F32 = 1, A0_MFMA_BF16X3 = 2 };
+enum { A0_VALU = 0, A0_MFMA_F32 = 1, A0_MFMA_BF16X6 = 2 };
 
 struct OmpParams {
     const float *X;
@@ -95,7 +96,7 @@ struct PropDev {
 hipError_t launch_dict_check(const float *D, int d, int K, int normalize, float *Dcopy, int *status,
                              hipStream_t st);
 hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *DT, uint16_t *Dbf, uint16_t *Dlo,
-                               float *D48, hipStream_t st);
+                               uint16_t *Dl2, float *D48, hipStream_t st);
 hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, double *G64, hipStream_t st);
 hipError_t launch_omp_batch(const DictDev &dict, const OmpParams &p, int kmax, int a0mode, int row_cache,
                             hipStream_t st);
@@ -173,6 +174,7 @@ struct sc_dict_s {
     float *G = nullptr;
     uint16_t *Dbf = nullptr;
     uint16_t *Dlo = nullptr;
+    uint16_t *Dl2 = nullptr;
     float *D48 = nullptr;   // K x 48 FP32, atoms padded to 16-byte rows
     double *G64 = nullptr;  // K x K FP64 Gram (the FP64 refit's entries)
     int *status = nullptr;

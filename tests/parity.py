@@ -14,10 +14,10 @@ count and coefficients are compared.  On every signal, the selections up to
 its first non-unique step are compared in order (the greedy choice is then
 the same on both sides, step by step).
 
-The same rule holds the split-BF16 precision form: its encoder re-correlates
-in FP32 every atom that its correlation error bound leaves in contention for
-the best one before it chooses, so its choices are those of the FP32
-correlations.
+The same rule holds the BF16 precision form: its six-product split-BF16
+correlations have the accuracy of FP32 dot products (error <= 4 * 2^-27
+||x|| from the products left out, plus FP32 accumulation), far below the
+margins compared.
 """
 import numpy as np
 

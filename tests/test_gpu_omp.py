@@ -103,7 +103,7 @@ def test_sh_like_workload_sample():
 MODES = [(0, sc.CORR_MFMA), (0, sc.CORR_VALU), (sc.PREC_BF16, None)]
 
 
-@pytest.mark.parametrize("flags,corr", MODES, ids=["fp32-mfma", "fp32-valu", "bf16x3"])
+@pytest.mark.parametrize("flags,corr", MODES, ids=["fp32-mfma", "fp32-valu", "bf16x6"])
 @pytest.mark.parametrize("K,k,eps,s", [(512, 12, 0.0, 4), (512, 12, 1e-2, 4), (128, 16, 0.0, 8),
                                        (256, 8, 1e-2, 4), (90, 12, 0.0, 6), (1000, 8, 0.0, 4),
                                        (640, 4, 0.0, 3), (48, 32, 0.0, 8)])
@@ -119,7 +119,7 @@ def test_dictionary_and_sparsity_shapes(K, k, eps, s, flags, corr):
     print(K, k, eps, flags, corr, r)
 
 
-@pytest.mark.parametrize("flags,corr", MODES, ids=["fp32-mfma", "fp32-valu", "bf16x3"])
+@pytest.mark.parametrize("flags,corr", MODES, ids=["fp32-mfma", "fp32-valu", "bf16x6"])
 def test_precision_modes_on_near_duplicates(flags, corr):
     """K=512, k=12, eps=0 with 5% near-duplicate signals (the precision
     workload's generator, 6000 signals)."""
