@@ -289,11 +289,13 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
     constexpr int kRowBatch = RCQ > 0 ? 1 : (KMAX >= 16 ? 2 : 3);   // within 128 VGPRs (4 waves per SIMD)
     const int d = dict.d, K = dict.K;
-    // k is re-read as an opaque scalar per signal, so the per-step tests
-    // against it are made where they are used rather than hoisted out of the
-    // signal loop (twelve hoisted masks would be spilled)
+    // k and the lane index are re-read as opaque values per signal, so the
+    // per-step tests against them are made where they are used rather than
+    // hoisted out of the signal loop (twelve hoisted masks would be spilled)
     int k = p.k;
     asm volatile("" : "+s"(k));
+    int lane_t = lane;   // the lane index for the tests lane < it, likewise opaque
+    asm volatile("" : "+v"(lane_t));
     const float *__restrict__ G = dict.G;
     const float *__restrict__ Dg = dict.D;
     const float xv = lane < d ? Xt[lane * xt_stride(T) + s] : 0.f;
@@ -345,9 +347,9 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     int n = 0, n_gam = 0;   // gamma is current for n_gam atoms
     bool active = xx > 0.f, expl_done = false;
 
-    // gamma = L^-T c for the first nn atoms: gamma_t is read from lane t as
-    // soon as its accumulator holds the terms of the later steps, and written
-    // back into lane t, so the entries of L above the diagonal are never used.
+    // gamma = L^-T c for the first nn atoms.  Lane t's accumulator stops
+    // changing once step t is passed (column t of L is zero above the
+    // diagonal), so every lane forms its own gamma_t at the end.
     auto back_sub = [&](int nn) {
         float acc = 0.f;
 #pragma unroll
@@ -355,9 +357,9 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             if (t < nn) {
                 const float gt = readlane_f((cval - acc) * linv, t);
                 acc = fmaf(Lcol[t], gt, acc);
-                gam = writelane_f(gt, t, gam);   // lane t: gamma_t
             }
         }
+        gam = (cval - acc) * linv;
         n_gam = nn;
     };
     // ||x - D_I gamma||^2 with the current gamma (lane i < d holds x_i)
@@ -492,9 +494,8 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         // ---- new row of the Cholesky factor: L w = G[I, j] ----
         const float g = G[(size_t)selv * Kp + j];   // lanes >= it read an unused entry of row 0
         const float gjj = G[(size_t)j * Kp + j];
-        // w_t is read from lane t once its accumulator holds the earlier
-        // terms; lane t keeps w_t (wv) and lane `it` the new row of L
-        float acc = 0.f, wsq = 0.f, wc = 0.f, wv = 0.f;
+        // lane `it` receives the new row of L
+        float acc = 0.f, wsq = 0.f, wc = 0.f;
 #pragma unroll
         for (int t = 0; t < it; ++t) {
             const float wt = readlane_f((g - acc) * linv, t);
@@ -502,8 +503,10 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             wsq = fmaf(wt, wt, wsq);
             wc = fmaf(wt, readlane_f(cval, t), wc);
             Lrow[t] = writelane_f(wt, it, Lrow[t]);
-            wv = writelane_f(wt, t, wv);
         }
+        // lane t < it holds w_t (its accumulator is final once step t is
+        // passed, as row t of L is zero right of the diagonal)
+        const float wv = lane_t < it ? (g - acc) * linv : 0.f;
         const float l2 = gjj - wsq;
         if (!(l2 > 1e-9f * gjj)) {   // numerically dependent on the selected atoms
             active = false;
