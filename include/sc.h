@@ -434,14 +434,25 @@ int sc_csc_fill(const int32_t *idx, const float *coef, const int32_t *count, int
 
 /*
  * sc_omp_encode_csc -- the tolerance-controlled encoder writing CSC (Sec. 2.2
- * with the eps-controlled sparsity of Sec. 3.2): sc_omp_encode into a
- * padded workspace, then the column pointers and the variable-length columns
- * in colptr (device int64[N+1]) / rows / vals.  *nnz_out (host) receives the
- * number of non-zeros; if it exceeds cap the call returns SC_ENOMEM after
- * writing colptr, so the caller can size rows/vals (cap = N * k always
- * suffices) and call again.  resid (device float32[N]) may be NULL.
- * workspace: device, >= sc_omp_encode_csc_workspace(N, k) bytes.
- * Synchronises `stream` once (to read the non-zero count).
+ * with the eps-controlled sparsity of Sec. 3.2) in one pass: no padded
+ * N x k codes exist anywhere.  Workgroups take 16-signal tiles in increasing
+ * order, encode them (same pursuit and results as sc_omp_encode), and find
+ * each tile's column offset from the counts of the tiles before it; the
+ * columns are written straight to colptr (device int64[N+1]) / rows / vals,
+ * in selection order.  Supports refit in FP64 (unless SC_NO_FP64_REFIT) get
+ * their coefficients solved again in place by a second pass.
+ *   cap       capacity of rows / vals (entries); they may be NULL when cap = 0
+ *   *nnz_out  (host) the number of non-zeros.  If it exceeds cap the call
+ *             returns SC_ENOMEM after writing colptr completely (rows / vals
+ *             hold the entries below cap), so the caller can size the arrays
+ *             (cap = N * k always suffices) and call again.
+ *   resid     device float32[N] or NULL
+ *   workspace device, >= sc_omp_encode_csc_workspace(N, k) bytes (8 bytes per
+ *             16 signals, plus 256); calls sharing it must not overlap
+ *   flags     SC_EPS_RELATIVE, SC_PREC_BF16, SC_NO_FP64_REFIT
+ * Synchronises `stream` once (to read the non-zero count).  Errors: SC_EINVAL,
+ * SC_ENOMEM, SC_EDEVICE (including a column-offset wait that exceeded its
+ * bound, reported in sc_last_error()).
  */
 size_t sc_omp_encode_csc_workspace(int64_t N, int k);
 int sc_omp_encode_csc(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, int64_t *colptr,

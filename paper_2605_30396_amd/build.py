@@ -35,6 +35,8 @@ EXTRA = {
     "omp_batch_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "omp_batch_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "omp_multi.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "omp_csc_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "omp_csc_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

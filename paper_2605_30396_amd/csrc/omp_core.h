@@ -281,10 +281,12 @@ __device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)
 // registers (RCQ * E VGPRs).  The row of the newest atom is fetched as soon
 // as the atom is chosen and held for the next step; older rows are re-read
 // kRowBatch at a time whenever alpha is formed.
+// The code goes to oidx / ocoef (k slots each) and *ocount; the residual to
+// p.resid[sig].
 template <int E, int KMAX, int T, int RCQ>
 __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams &p, int64_t sig, int s,
                                             const float *__restrict__ Xt, const float *__restrict__ A0, int lane,
-                                            OmpTally &tally) {
+                                            int32_t *oidx, float *ocoef, int32_t *ocount, OmpTally &tally) {
     constexpr int Kp = 64 * E;
     constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
     constexpr int kRowBatch = RCQ > 0 ? 1 : (KMAX >= 16 ? 2 : 3);   // within 128 VGPRs (4 waves per SIMD)
@@ -300,15 +302,13 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     const float *__restrict__ Dg = dict.D;
     const float xv = lane < d ? Xt[lane * xt_stride(T) + s] : 0.f;
     const int dl = lane < d ? lane : d - 1;   // in-bounds row offset for the idle lanes
-    int32_t *oidx = p.idx + sig * k;
-    float *ocoef = p.coef + sig * k;
     if (ballot(lane < d && !isfinite(xv)) != 0) {   // status -1, padded slots
         if (lane < k) {
             oidx[lane] = -1;
             ocoef[lane] = 0.f;
         }
         if (lane == 0) {
-            p.count[sig] = -1;
+            *ocount = -1;
             if (p.resid) p.resid[sig] = __builtin_nanf("");
         }
         return;
@@ -537,19 +537,28 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         ocoef[lane] = lane < n ? gam : 0.f;
     }
     if (lane == 0) {
-        p.count[sig] = refit ? -(2 + n) : n;
+        *ocount = refit ? -(2 + n) : n;
         if (p.resid) p.resid[sig] = refit ? 0.f : __builtin_amdgcn_sqrtf(re);
     }
     tally.sig += 1;
     tally.atoms += n;
 }
 
+// Codes staged in LDS instead of written to p.idx / p.coef / p.count: slot
+// s of the tile at idx[s k ..], coef[s k ..], cnt[s].
+struct CodeStage {
+    int32_t *idx;
+    float *coef;
+    int32_t *cnt;
+};
+
 // One tile of T signals: load, alpha0 by `mode` (A0_VALU or A0_MFMA_F32; or
 // A0_MFMA_BF16X6 when kSplitOK, T == 16 and the LDS holds the split parts),
-// then each wave encodes its signals.
+// then each wave encodes its signals (into `stage` when given).
 template <int E, int KMAX, int T, bool kSplitOK, int RCQ>
 __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p, int mode, int64_t s0, int nt,
-                                         unsigned char *smem, int tid, OmpTally &tally) {
+                                         unsigned char *smem, int tid, OmpTally &tally,
+                                         const CodeStage *stage = nullptr) {
     constexpr int Kp = 64 * E;
     float *A0 = reinterpret_cast<float *>(smem);
     float *Xt = A0 + T * a0_stride(Kp);
@@ -587,7 +596,12 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
     for (int s = wave; s < nt; s += kOmpWaves) {
         const int64_t sig = p.rows ? (int64_t)p.rows[s0 + s] : s0 + s;
         if (p.rows && (uint64_t)sig >= (uint64_t)p.N) continue;   // out-of-range list entry: skipped
-        omp_pursuit<E, KMAX, T, RCQ>(dict, p, sig, s, Xt, A0, lane, tally);
+        if (stage)
+            omp_pursuit<E, KMAX, T, RCQ>(dict, p, sig, s, Xt, A0, lane, stage->idx + s * p.k, stage->coef + s * p.k,
+                                         stage->cnt + s, tally);
+        else
+            omp_pursuit<E, KMAX, T, RCQ>(dict, p, sig, s, Xt, A0, lane, p.idx + sig * p.k, p.coef + sig * p.k,
+                                         p.count + sig, tally);
     }
 }
 
@@ -617,14 +631,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Cholesky factorisation, all lane-parallel in LDS: G_II is gathered from the
 // dictionary's FP64 Gram (row t by lanes u <= t), the selected atoms are
 // staged once for D_I^T x and the residual, and each factorisation /
-// substitution step updates its trailing entries in parallel.  Writes gamma,
-// the explicit residual and count = n.
-__device__ __forceinline__ void refit_one(const DictDev &dict, const OmpParams &p, int64_t sig, int n,
-                                          RefitScratch &ws, int lane) {
-    const int d = dict.d, k = p.k;
+// substitution step updates its trailing entries in parallel.  The n atoms
+// are read from sel_in, gamma is written to coef_out; returns the explicit
+// ||x - D_I gamma||^2 (on every lane).
+__device__ __forceinline__ double refit_codes(const DictDev &dict, const float *__restrict__ x,
+                                              const int32_t *sel_in, float *coef_out, int n, RefitScratch &ws,
+                                              int lane) {
+    const int d = dict.d;
     const float *__restrict__ D = dict.D;
-    const float *__restrict__ x = p.X + sig * d;
-    if (lane < n) ws.sel[lane] = p.idx[sig * k + lane];
+    if (lane < n) ws.sel[lane] = sel_in[lane];
     if (lane < d) ws.xs[lane] = x[lane];
     wave_lds_sync();
     for (int q = lane; q < n * d; q += 64) {
@@ -683,12 +698,19 @@ __device__ __forceinline__ void refit_one(const DictDev &dict, const OmpParams &
         for (int t = 0; t < n; ++t) r -= z[t] * (double)ws.Di[t * 64 + lane];
     }
     const double r2 = wave_sum_d(lane < d ? r * r : 0.0);
-    if (lane < n) p.coef[sig * k + lane] = (float)z[lane];
+    if (lane < n) coef_out[lane] = (float)z[lane];
+    __builtin_amdgcn_wave_barrier();
+    return r2;
+}
+
+// FP64 refit of a flagged padded code: gamma, the explicit residual and count = n.
+__device__ __forceinline__ void refit_one(const DictDev &dict, const OmpParams &p, int64_t sig, int n,
+                                          RefitScratch &ws, int lane) {
+    const double r2 = refit_codes(dict, p.X + sig * dict.d, p.idx + sig * p.k, p.coef + sig * p.k, n, ws, lane);
     if (lane == 0) {
         p.count[sig] = n;
         if (p.resid) p.resid[sig] = (float)sqrt(r2);
     }
-    __builtin_amdgcn_wave_barrier();
 }
 
 // Scans the call's signals in chunks of 64 (wave `gw` of `nw` waves) and

@@ -318,8 +318,7 @@ int sc_csc_fill(const int32_t *idx, const float *coef, const int32_t *count, int
 
 size_t sc_omp_encode_csc_workspace(int64_t N, int k) {
     if (N < 0 || k < 1 || k > 32) return 0;
-    return align_up(sizeof(int32_t) * (size_t)N * k) * 2 + align_up(sizeof(int32_t) * (size_t)N) +
-           align_up(sizeof(float) * (size_t)N) + sc_csc_workspace(N) + kAlign;
+    return align_up(sc::csc_encode_workspace_bytes(N));
 }
 
 int sc_omp_encode_csc(sc_dict h, const float *X, int64_t N, int k, float eps, int flags, int64_t *colptr,
@@ -327,29 +326,41 @@ int sc_omp_encode_csc(sc_dict h, const float *X, int64_t N, int k, float eps, in
                       size_t ws_bytes, void *stream) {
     if (!h || N < 0 || cap < 0 || !colptr || !nnz_out) return SC_EINVAL;
     if (k < 1 || k > std::min(std::min(h->dev.K, h->dev.d), 32)) return SC_EINVAL;
+    if (!(eps >= 0.f) || !isfinite(eps)) return SC_EINVAL;
+    if (flags & ~(SC_EPS_RELATIVE | SC_PREC_BF16 | SC_NO_FP64_REFIT)) return SC_EINVAL;
     if (!workspace) return SC_EINVAL;
     if (ws_bytes < sc_omp_encode_csc_workspace(N, k)) return SC_ENOMEM;
+    if (N > 0 && !X) return SC_EINVAL;
+    if (cap > 0 && (!rows || !vals)) return SC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    unsigned char *w = (unsigned char *)workspace;
-    int32_t *idx = (int32_t *)w;
-    w += align_up(sizeof(int32_t) * (size_t)N * k);
-    float *coef = (float *)w;
-    w += align_up(sizeof(int32_t) * (size_t)N * k);
-    int32_t *count = (int32_t *)w;
-    w += align_up(sizeof(int32_t) * (size_t)N);
-    float *res = resid ? resid : (float *)w;
-    w += align_up(sizeof(float) * (size_t)N);
-    int rc = sc_omp_encode(h, X, N, k, eps, flags, idx, coef, count, res, stream);
-    if (rc != SC_OK) return rc;
-    rc = sc_csc_colptr(count, N, colptr, w, sc_csc_workspace(N), stream);
-    if (rc != SC_OK) return rc;
+    const size_t wsz = sc::csc_encode_workspace_bytes(N);
+    SC_HIP(sc::launch_zero_words(workspace, (int64_t)(wsz / 4), st), "sc_omp_encode_csc");
+    if (N == 0) {
+        SC_HIP(sc::launch_zero_words(colptr, 2, st), "sc_omp_encode_csc");
+    } else {
+        sc::OmpParams p{X, N, nullptr, nullptr, k, eps, (flags & SC_EPS_RELATIVE) ? 1 : 0,
+                        (flags & SC_NO_FP64_REFIT) ? 0 : 1, kKappaMax, nullptr, nullptr, nullptr, resid, h->stats};
+        const int a0 = (flags & SC_PREC_BF16) ? sc::A0_MFMA_BF16X6 : h->a0_fp32;
+        hipError_t e = sc::launch_omp_csc(h->dev, p, sc::pick_kmax(k), a0, row_cache_for(h, flags), colptr, rows, vals,
+                                          cap, workspace, st);
+        if (e == hipErrorInvalidValue) {
+            snprintf(g_last_error, sizeof(g_last_error), "no compiled CSC encoder for K=%d with k=%d", h->dev.K, k);
+            return SC_EINVAL;
+        }
+        if (e != hipSuccess) return set_dev_error("sc_omp_encode_csc", e);
+    }
     int64_t nnz = 0;
+    int err = 0;
     SC_HIP(hipMemcpyAsync(&nnz, colptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, st), "sc_omp_encode_csc");
+    SC_HIP(hipMemcpyAsync(&err, (unsigned char *)workspace + sizeof(int), sizeof(int), hipMemcpyDeviceToHost, st),
+           "sc_omp_encode_csc");
     SC_HIP(hipStreamSynchronize(st), "sc_omp_encode_csc");
     *nnz_out = nnz;
-    if (nnz > cap) return SC_ENOMEM;
-    if (nnz > 0 && (!rows || !vals)) return SC_EINVAL;
-    return N > 0 ? sc_csc_fill(idx, coef, count, N, k, colptr, rows, vals, stream) : SC_OK;
+    if (err) {
+        snprintf(g_last_error, sizeof(g_last_error), "sc_omp_encode_csc: a column-offset wait exceeded its bound");
+        return SC_EDEVICE;
+    }
+    return nnz > cap ? SC_ENOMEM : SC_OK;
 }
 
 int sc_sh_eval_csc(sc_dict h, const int64_t *colptr, const int32_t *rows, const float *vals, int64_t N,

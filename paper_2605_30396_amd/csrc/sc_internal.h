@@ -104,6 +104,12 @@ hipError_t launch_omp_batch_valu(const DictDev &dict, const OmpParams &p, int km
 hipError_t launch_omp_batch_mfma(const DictDev &dict, const OmpParams &p, int kmax, int row_cache, hipStream_t st);
 hipError_t launch_omp_batch_bf16(const DictDev &dict, const OmpParams &p, int kmax, int row_cache, hipStream_t st);
 hipError_t launch_omp_refit(const DictDev &dict, const OmpParams &p, hipStream_t st);
+// One-pass encoder into CSC (p.idx / p.coef / p.count unused); ws holds
+// csc_encode_workspace_bytes(N) bytes whose first 256 bytes and descriptors
+// are zero.
+size_t csc_encode_workspace_bytes(int64_t N);
+hipError_t launch_omp_csc(const DictDev &dict, const OmpParams &p, int kmax, int a0mode, int row_cache,
+                          int64_t *colptr, int32_t *rows, float *vals, int64_t cap, void *ws, hipStream_t st);
 hipError_t launch_omp_multi(const sc_scene *scenes, const int *order, int n, int a0mode, int tile, int row_cache,
                             int wg_per_cu, int *counter, hipStream_t st);
 hipError_t launch_omp_restricted(const DictDev &dict, const float *D48, const RompParams &p, int kmax,

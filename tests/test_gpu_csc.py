@@ -141,3 +141,97 @@ def test_encode_straight_to_csc():
         sc.omp_encode_csc(h, Xg, k, tol, sc.EPS_RELATIVE, cap=nnz - 1)
     assert e.value.code == sc.SC_ENOMEM
     h.destroy()
+
+
+def _csc_columns_against_oracle(D, X, k, eps, relative, colptr, rows, vals, resid):
+    """Column by column against the oracle's OMP packed by the oracle's CSC
+    packing: exact on signals whose greedy path is unique, valid everywhere
+    (least-squares fit on the column's own support, residual reported)."""
+    from parity import oracle_run, unique_prefix, well_separated
+    ref = oracle_run(D, X, k, eps, relative)
+    rc, rr, rv = oracle.pack_csc(ref["idx"], ref["coef"], ref["count"])
+    sep = well_separated(D, X, ref, eps, relative)
+    pre = unique_prefix(D, X, ref, eps, relative)
+    assert colptr[0] == 0 and np.all(np.diff(colptr) >= 0)
+    cnt = np.diff(colptr)
+    np.testing.assert_array_equal(cnt[sep], np.diff(rc)[sep])
+    Dd, Xd = D.astype(np.float64), X.astype(np.float64)
+    worst = 0.0
+    for i in range(len(X)):
+        a, b = colptr[i], colptr[i + 1]
+        S, c = rows[a:b], vals[a:b].astype(np.float64)
+        # selections in order up to the first non-unique step
+        np.testing.assert_array_equal(S[:pre[i]], rr[rc[i]:rc[i] + pre[i]], err_msg=f"column {i} prefix")
+        if sep[i]:
+            np.testing.assert_array_equal(S, rr[rc[i]:rc[i + 1]], err_msg=f"column {i}")
+            ro = rv[rc[i]:rc[i + 1]].astype(np.float64)
+            worst = max(worst, np.linalg.norm(c - ro) / max(np.linalg.norm(ro), 1e-30))
+        if ref["count"][i] < 0:
+            assert b == a and np.isnan(resid[i])
+            continue
+        if b > a:
+            r = Xd[i] - c @ Dd[S]
+            assert abs(np.linalg.norm(r) - resid[i]) <= 1e-5 * (np.linalg.norm(Xd[i]) + 1e-30)
+            if np.linalg.cond(Dd[S] @ Dd[S].T) <= 1e3:
+                g = np.linalg.lstsq(Dd[S].T, Xd[i], rcond=None)[0]
+                assert np.linalg.norm(c - g) <= 1e-4 * max(np.linalg.norm(g), 1e-30), i
+    assert worst <= 1e-4, worst
+    return sep, pre.sum() / max(int(np.maximum(ref["count"], 0).sum()), 1)
+
+
+@pytest.mark.parametrize("N", [1, 16, 4097])
+def test_one_pass_csc_encoder_against_oracle(N):
+    """sc_omp_encode_csc at a relative tolerance (the codes' length varies),
+    k = 32, SH-like signals over the K = 256 MOD dictionary: every column
+    equals the oracle's OMP packed by the oracle's CSC packing on signals
+    whose greedy path is unique, and is a valid code elsewhere; a NaN signal
+    is an empty column."""
+    K, k, tol = 256, 32, 0.1
+    X = I.sh_like_signals(I.rng_for(560 + N), N)
+    if N > 16:
+        X[5, 3] = np.nan
+    D = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sh_like_dict_K256.npy"))
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    colptr, rows, vals, resid = (t.cpu().numpy() for t in sc.omp_encode_csc(h, torch.from_numpy(X).to(DEV), k,
+                                                                            tol, sc.EPS_RELATIVE))
+    sep, steps = _csc_columns_against_oracle(D, X, k, tol, True, colptr, rows, vals, resid)
+    assert N <= 16 or (sep.mean() > 0.1 and steps > 0.5), (sep.mean(), steps)   # 16% and 60% here
+    lens = np.diff(colptr)
+    assert N < 16 or lens.min() < lens.max()   # variable-length columns
+    h.destroy()
+
+
+def test_one_pass_csc_encoder_sparse_and_refit():
+    """4-sparse signals over a K = 512 dictionary at eps = 1e-2 (columns of
+    about four atoms, 200 tiles), plus a support refit in FP64 inside the
+    same call (its column pointer is restored and its coefficients are the
+    FP64 fit); a second call with too small a capacity reports the size and
+    leaves colptr whole."""
+    K, k, eps = 512, 12, 1e-2
+    rng = I.rng_for(570)
+    D = I.random_dictionary(rng, K)
+    X, _, _ = I.sparse_signals(rng, D, 3200, 4, 1e-3)
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    Xg = torch.from_numpy(X).to(DEV)
+    colptr, rows, vals, resid = (t.cpu().numpy() for t in sc.omp_encode_csc(h, Xg, k, eps))
+    _csc_columns_against_oracle(D, X, k, eps, False, colptr, rows, vals, resid)
+    nnz = int(colptr[-1])
+    with pytest.raises(sc.ScError) as e:
+        sc.omp_encode_csc(h, Xg, k, eps, cap=nnz // 2)
+    assert e.value.code == sc.SC_ENOMEM
+    h.destroy()
+    # ill-conditioned support: a1 = e1, a2 = normalise(e1 + 1e-3 e2), a3 = e3; x = e2
+    a2 = np.array([1.0, 1e-3, 0.0]) / np.sqrt(1 + 1e-6)
+    Dill = np.array([[1, 0, 0], a2, [0, 0, 1]], np.float32)
+    Xill = np.tile(np.array([[0, 1, 0]], np.float32), (40, 1))
+    h = sc.gram_precompute(torch.from_numpy(Dill).to(DEV))
+    sc.omp_stats(h, reset=True)
+    colptr, rows, vals, resid = (t.cpu().numpy() for t in sc.omp_encode_csc(h, torch.from_numpy(Xill).to(DEV), 2, 0.0))
+    assert sc.omp_stats(h)["fp64_refits"] == 40
+    ref = oracle.omp(Dill, Xill[:1], 2)
+    assert np.all(colptr == 2 * np.arange(41))
+    for i in range(40):
+        np.testing.assert_array_equal(rows[2 * i:2 * i + 2], ref["idx"][0])
+        err = np.linalg.norm(vals[2 * i:2 * i + 2] - ref["coef"][0]) / np.linalg.norm(ref["coef"][0])
+        assert err <= 1e-4, (i, err)
+    h.destroy()
