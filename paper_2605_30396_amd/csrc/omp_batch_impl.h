@@ -7,27 +7,38 @@
 
 namespace sc {
 
-constexpr int kTileS = 16;   // signals per workgroup tile
+// Workgroup shape: the FP32 MFMA correlation of dictionaries of 128..512
+// atoms runs 8 waves on 32-signal tiles, so every dictionary read from the
+// cache feeds twice the signals (the correlation stage is bound by those
+// reads); the LDS tile (75 KB at K = 512) still lets two workgroups share a
+// compute unit.  Every other case runs 4 waves on 16-signal tiles.
+template <int E, int MODE>
+struct BatchShape {
+    static constexpr int NW = (MODE == A0_MFMA_F32 && E >= 2 && E <= 8) ? 8 : kOmpWaves;
+    static constexpr int T = 4 * NW;
+};
 
 template <int E, int KMAX, int MODE, int RCQ>
-__global__ __launch_bounds__(kOmpThreads) void omp_batch_kernel(DictDev dict, OmpParams p) {
+__global__ __launch_bounds__((64 * BatchShape<E, MODE>::NW)) __attribute__((amdgpu_waves_per_eu(4)))
+void omp_batch_kernel(DictDev dict, OmpParams p) {
+    constexpr int NW = BatchShape<E, MODE>::NW, T = BatchShape<E, MODE>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     OmpTally tally;
     int64_t Nsig = p.N;
     if (p.rows) Nsig = min<int64_t>(Nsig, (int64_t)*p.nrows);
-    const int64_t ntiles = (Nsig + kTileS - 1) / kTileS;
+    const int64_t ntiles = (Nsig + T - 1) / T;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t s0 = tile * kTileS;
-        const int nt = (int)min<int64_t>(kTileS, Nsig - s0);
+        const int64_t s0 = tile * T;
+        const int nt = (int)min<int64_t>(T, Nsig - s0);
         // thread-derived addresses are recomputed per tile rather than held
         // live across the loop
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        omp_tile<E, KMAX, kTileS, MODE == A0_MFMA_BF16X6, RCQ>(dict, p, MODE, s0, nt, smem_raw, tid, tally);
+        omp_tile<E, KMAX, T, MODE == A0_MFMA_BF16X6, RCQ, NW>(dict, p, MODE, s0, nt, smem_raw, tid, tally);
     }
     // counters: one pair of atomics per workgroup (device-wide atomics on one
     // address serialise, and every wave ends at about the same time)
-    __shared__ unsigned long long red[kOmpWaves][2];
+    __shared__ unsigned long long red[NW][2];
     if (p.stats) {
         if ((threadIdx.x & 63) == 0) {
             red[threadIdx.x >> 6][0] = tally.sig;
@@ -36,7 +47,7 @@ __global__ __launch_bounds__(kOmpThreads) void omp_batch_kernel(DictDev dict, Om
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long sg = 0, at = 0;
-            for (int w = 0; w < kOmpWaves; ++w) {
+            for (int w = 0; w < NW; ++w) {
                 sg += red[w][0];
                 at += red[w][1];
             }
@@ -57,8 +68,8 @@ inline int device_cus() {
 
 template <int E, int KMAX, int MODE, int RCQ>
 static hipError_t launch_batch_t(const DictDev &dict, const OmpParams &p, hipStream_t st) {
-    constexpr int Kp = 64 * E;
-    const size_t smem = omp_tile_lds(kTileS, Kp, MODE == A0_MFMA_BF16X6);
+    constexpr int Kp = 64 * E, NW = BatchShape<E, MODE>::NW, T = BatchShape<E, MODE>::T;
+    const size_t smem = omp_tile_lds(T, Kp, MODE == A0_MFMA_BF16X6);
     auto kern = omp_batch_kernel<E, KMAX, MODE, RCQ>;
     static bool attr_set = false;
     if (!attr_set) {
@@ -66,13 +77,13 @@ static hipError_t launch_batch_t(const DictDev &dict, const OmpParams &p, hipStr
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const int64_t ntiles = (p.N + kTileS - 1) / kTileS;   // upper bound in list mode
+    const int64_t ntiles = (p.N + T - 1) / T;   // upper bound in list mode
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kOmpThreads, smem) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 64 * NW, smem) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus() * per_cu);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kOmpThreads), smem, st, dict, p);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * NW), smem, st, dict, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !p.fp64_refit) return e;
     return launch_omp_refit(dict, p, st);

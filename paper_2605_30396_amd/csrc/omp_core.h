@@ -75,22 +75,23 @@ struct OmpTally {
 
 // Signals s0 .. s0+nt-1 of the call (through `rows` when given), stored
 // feature-major Xt[i][s]; features >= d and columns >= nt are zero.
-template <int T>
+template <int T, int NW = kOmpWaves>
 __device__ __forceinline__ void load_tile(const OmpParams &p, int d, int64_t s0, int nt, float *Xt, int tid) {
+    constexpr int NT = 64 * NW;
     if (p.rows) {   // a listed row outside [0, N) reads as zeros (and is not encoded)
-        for (int f = tid; f < nt * d; f += kOmpThreads) {
+        for (int f = tid; f < nt * d; f += NT) {
             const int s = f / d, i = f - s * d;
             const int64_t r = p.rows[s0 + s];
             Xt[i * xt_stride(T) + s] = (uint64_t)r < (uint64_t)p.N ? p.X[r * d + i] : 0.f;
         }
     } else {
         const float *__restrict__ Xtile = p.X + s0 * d;
-        for (int f = tid; f < nt * d; f += kOmpThreads) {
+        for (int f = tid; f < nt * d; f += NT) {
             const int s = f / d, i = f - s * d;
             Xt[i * xt_stride(T) + s] = Xtile[f];
         }
     }
-    for (int q = tid; q < 64 * T; q += kOmpThreads) {
+    for (int q = tid; q < 64 * T; q += NT) {
         const int i = q / T, s = q - i * T;
         if (i >= d || s >= nt) Xt[i * xt_stride(T) + s] = 0.f;
     }
@@ -100,12 +101,12 @@ __device__ __forceinline__ void load_tile(const OmpParams &p, int d, int64_t s0,
 // rows are read from L2 four features ahead of their use (a ring of four row
 // slices in registers), so the L2 latency overlaps the FMAs of the features
 // in between instead of stalling every feature.
-template <int E, int T>
+template <int E, int T, int NW = kOmpWaves>
 __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d, const float *__restrict__ Xt,
                                             float *__restrict__ A0, int tid) {
-    constexpr int Kp = 64 * E;
-    constexpr int KpP = Kp < kOmpThreads ? Kp : kOmpThreads;   // atoms covered by one pass of the workgroup
-    constexpr int SG = kOmpThreads / KpP;                      // signal groups
+    constexpr int Kp = 64 * E, NT = 64 * NW;
+    constexpr int KpP = Kp < NT ? Kp : NT;   // atoms covered by one pass of the workgroup
+    constexpr int SG = NT / KpP;             // signal groups
     constexpr int JS = Kp / KpP;                               // atom slots per thread
     constexpr int SQ = T / SG;                                 // signals per thread
     constexpr int PF = 4;                                      // prefetch distance (features)
@@ -160,53 +161,56 @@ __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d,
 }
 
 // alpha0 tile on FP32 MFMA (v_mfma_f32_16x16x4_f32): wave w computes the
-// 16-atom blocks w, w+4, ... for every 16-signal column block.  A operand:
-// 16 atoms x 4 features read from the feature-major dictionary, one k-step
-// ahead of its use; B operand: 4 features x 16 signals from the LDS signal
-// tile.
-template <int E, int T>
-__device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ DT, int d, const float *__restrict__ Xt,
+// 16-atom blocks w, w+NW, ... for every 16-signal column block.  The
+// contraction runs over 16-feature chunks whose four k-steps take features
+// 4 kq + s (s = 0..3) in lane group kq, so the A operands of a whole chunk are
+// one 16-byte read per lane from the atom-major dictionary Dr (Kp x dpad,
+// zero padded): a wave's reads cover whole atom rows, and the next chunk is
+// read while the current one is multiplied.  B operands come from the
+// feature-major signal tile in LDS.
+template <int E, int T, int NW = kOmpWaves>
+__device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, int dpad, const float *__restrict__ Xt,
                                                 float *__restrict__ A0, int wave, int lane) {
-    constexpr int Kp = 64 * E, MT = Kp / 16, NB = MT / kOmpWaves, CB = T / 16;
-    static_assert(T % 16 == 0, "MFMA tile needs 16-signal column blocks");
+    constexpr int Kp = 64 * E, MT = Kp / 16, NB = MT / NW, CB = T / 16;
+    static_assert(T % 16 == 0 && MT % NW == 0 && NB >= 1, "MFMA tile shape");
     const int lr = lane & 15, kq = lane >> 4;
     floatx4 acc[NB][CB];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int c = 0; c < CB; ++c) acc[b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // DT holds dt_rows(d) rows, those past d zero, so the next k-step's
-    // operands are read without a bound test.
-    const int dk = (d + 3) & ~3;
-    float an[NB];
-    {
-        const float *row = DT + (size_t)kq * Kp + lr;
+    const float *rowp[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) an[b] = row[(wave + kOmpWaves * b) * 16];
-    }
-    for (int k0 = 0; k0 < dk; k0 += 4) {
-        float a[NB];
+    for (int b = 0; b < NB; ++b) rowp[b] = Dr + (size_t)((wave + NW * b) * 16 + lr) * dpad + 4 * kq;
+    floatx4 an[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) an[b] = *reinterpret_cast<const floatx4 *>(rowp[b]);
+    for (int f0 = 0; f0 < dpad; f0 += 16) {
+        floatx4 a[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) a[b] = an[b];
-        {
-            const float *row = DT + (size_t)(k0 + 4 + kq) * Kp + lr;
+        if (f0 + 16 < dpad) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) an[b] = row[(wave + kOmpWaves * b) * 16];
+            for (int b = 0; b < NB; ++b) an[b] = *reinterpret_cast<const floatx4 *>(rowp[b] + f0 + 16);
         }
-        const int f = k0 + kq;
-        float bx[CB];
 #pragma unroll
-        for (int c = 0; c < CB; ++c) bx[c] = Xt[f * xt_stride(T) + c * 16 + lr];
+        for (int q = 0; q < 4; ++q) {
+            const int f = f0 + 4 * kq + q;
+            float bx[CB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+            for (int c = 0; c < CB; ++c) bx[c] = Xt[f * xt_stride(T) + c * 16 + lr];
 #pragma unroll
-            for (int c = 0; c < CB; ++c) acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b], bx[c], acc[b][c], 0, 0, 0);
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b][q], bx[c], acc[b][c], 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-            *reinterpret_cast<floatx4 *>(A0 + (c * 16 + lr) * a0_stride(Kp) + (wave + kOmpWaves * b) * 16 + 4 * kq) =
+            *reinterpret_cast<floatx4 *>(A0 + (c * 16 + lr) * a0_stride(Kp) + (wave + NW * b) * 16 + 4 * kq) =
                 acc[b][c];
 }
 
@@ -555,7 +559,7 @@ struct CodeStage {
 // One tile of T signals: load, alpha0 by `mode` (A0_VALU or A0_MFMA_F32; or
 // A0_MFMA_BF16X6 when kSplitOK, T == 16 and the LDS holds the split parts),
 // then each wave encodes its signals (into `stage` when given).
-template <int E, int KMAX, int T, bool kSplitOK, int RCQ>
+template <int E, int KMAX, int T, bool kSplitOK, int RCQ, int NW = kOmpWaves>
 __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p, int mode, int64_t s0, int nt,
                                          unsigned char *smem, int tid, OmpTally &tally,
                                          const CodeStage *stage = nullptr) {
@@ -565,14 +569,14 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the signal loop below is per wave
     __syncthreads();   // the previous tile is done with Xt and A0
-    load_tile<T>(p, dict.d, s0, nt, Xt, tid);
+    load_tile<T, NW>(p, dict.d, s0, nt, Xt, tid);
     __syncthreads();
     bool done = false;
     if constexpr (T % 16 == 0) {   // the MFMA stages work on 16-signal column blocks
         if (mode == A0_MFMA_F32) {
-            alpha0_mfma_f32<E, T>(dict.DT, dict.d, Xt, A0, wave, lane);
+            alpha0_mfma_f32<E, T, NW>(dict.Dr, dict.dpad, Xt, A0, wave, lane);
             done = true;
-        } else if (kSplitOK && T == 16 && mode == A0_MFMA_BF16X6) {
+        } else if (kSplitOK && T == 16 && NW == kOmpWaves && mode == A0_MFMA_BF16X6) {
             // signal parts [3][T][kXhs]: x = xh + xm + xl in BF16
             uint16_t *Xh = split_in_a0(T, Kp) ? reinterpret_cast<uint16_t *>(A0)
                                               : reinterpret_cast<uint16_t *>(Xt + 64 * xt_stride(T));
@@ -591,9 +595,9 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
             done = true;
         }
     }
-    if (!done) alpha0_valu<E, T>(dict.DT, dict.d, Xt, A0, tid);
+    if (!done) alpha0_valu<E, T, NW>(dict.DT, dict.d, Xt, A0, tid);
     __syncthreads();
-    for (int s = wave; s < nt; s += kOmpWaves) {
+    for (int s = wave; s < nt; s += NW) {
         const int64_t sig = p.rows ? (int64_t)p.rows[s0 + s] : s0 + s;
         if (p.rows && (uint64_t)sig >= (uint64_t)p.N) continue;   // out-of-range list entry: skipped
         if (stage)

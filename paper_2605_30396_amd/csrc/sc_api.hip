@@ -53,6 +53,7 @@ void free_dict(sc_dict h) {
     hipFree(h->Dbf);
     hipFree(h->Dlo);
     hipFree(h->Dl2);
+    hipFree(h->Dr);
     hipFree(h->D48);
     hipFree(h->G64);
     hipFree(h->status);
@@ -97,12 +98,14 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
     sc_dict h = new sc_dict_s();
     h->device = dev;
     const int Kp = 64 * E;
+    const int dpad = (d + 15) / 16 * 16;
     bool ok = hipMalloc(&h->D, sizeof(float) * (size_t)K * d) == hipSuccess &&
               hipMalloc(&h->DT, sizeof(float) * (size_t)sc::dt_rows(d) * Kp) == hipSuccess &&
               hipMalloc(&h->G, sizeof(float) * (size_t)K * Kp) == hipSuccess &&
               hipMalloc(&h->Dbf, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->Dlo, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->Dl2, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
+              hipMalloc(&h->Dr, sizeof(float) * (size_t)Kp * dpad) == hipSuccess &&
               hipMalloc(&h->D48, sizeof(float) * (size_t)K * 48) == hipSuccess &&
               hipMalloc(&h->G64, sizeof(double) * (size_t)K * K) == hipSuccess &&
               hipMalloc(&h->status, sizeof(int) * 4) == hipSuccess &&
@@ -131,13 +134,13 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
         return SC_ENORM;
     }
     if ((e = hipMemsetAsync(h->DT, 0, sizeof(float) * (size_t)sc::dt_rows(d) * Kp, st)) != hipSuccess ||
-        (e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->Dl2, h->D48, st)) != hipSuccess ||
+        (e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->Dl2, h->D48, h->Dr, dpad, st)) != hipSuccess ||
         (e = sc::launch_gram(h->D, d, K, Kp, h->G, h->G64, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         free_dict(h);
         return set_dev_error("sc_gram_precompute", e);
     }
-    h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->Dl2, h->D48, h->G64};
+    h->dev = sc::DictDev{d, K, Kp, E, h->D, h->DT, h->G, h->Dbf, h->Dlo, h->Dl2, h->D48, h->G64, h->Dr, dpad};
     h->row_cache = E <= 4 ? 4 : 0;
     h->row_cache_bf16 = h->row_cache;
     // device copy of the layout descriptor, read by the multi-scene encoder

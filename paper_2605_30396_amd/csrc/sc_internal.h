@@ -40,6 +40,8 @@ struct DictDev {
     const uint16_t *Dl2;  // Kp x 64 BF16 low part bf16(D - Dbf - Dlo)
     const float *D48;     // K x 48 FP32 atom-major, features zero padded (d <= 48)
     const double *G64;    // K x K Gram, exact products summed in FP64 (not rounded)
+    const float *Dr;      // Kp x dpad FP32 atom-major, atoms and features zero padded (MFMA operands)
+    int dpad;             // d rounded up to 16
 };
 
 // How the correlation tile alpha0 = D^T X is computed by the batch encoder.
@@ -96,7 +98,7 @@ struct PropDev {
 hipError_t launch_dict_check(const float *D, int d, int K, int normalize, float *Dcopy, int *status,
                              hipStream_t st);
 hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *DT, uint16_t *Dbf, uint16_t *Dlo,
-                               uint16_t *Dl2, float *D48, hipStream_t st);
+                               uint16_t *Dl2, float *D48, float *Dr, int dpad, hipStream_t st);
 hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, double *G64, hipStream_t st);
 hipError_t launch_omp_batch(const DictDev &dict, const OmpParams &p, int kmax, int a0mode, int row_cache,
                             hipStream_t st);
@@ -181,6 +183,7 @@ struct sc_dict_s {
     uint16_t *Dbf = nullptr;
     uint16_t *Dlo = nullptr;
     uint16_t *Dl2 = nullptr;
+    float *Dr = nullptr;    // Kp x dpad FP32 atom-major (MFMA operands)
     float *D48 = nullptr;   // K x 48 FP32, atoms padded to 16-byte rows
     double *G64 = nullptr;  // K x K FP64 Gram (the FP64 refit's entries)
     int *status = nullptr;
