@@ -161,19 +161,33 @@ __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d,
 }
 
 // alpha0 tile on FP32 MFMA (v_mfma_f32_16x16x4_f32): wave w computes the
-// 16-atom blocks w, w+NW, ... for every 16-signal column block.  The
-// contraction runs over 16-feature chunks whose four k-steps take features
+// 16-atom blocks w, w+NW, ... for every 16-signal column block; when there
+// are fewer atom blocks than waves, NW / MT waves share an atom block and
+// split the column blocks between them (each output element takes the same
+// MFMA sequence either way, so the values do not depend on the wave count).
+// The contraction runs over 16-feature chunks whose four k-steps take features
 // 4 kq + s (s = 0..3) in lane group kq, so the A operands of a whole chunk are
 // one 16-byte read per lane from the atom-major dictionary Dr (Kp x dpad,
 // zero padded): a wave's reads cover whole atom rows, and the next chunk is
 // read while the current one is multiplied.  B operands come from the
 // feature-major signal tile in LDS.
+template <int E, int T, int NW>
+struct MfmaF32Split {
+    static constexpr int MT = 16 * E / 4, CB = T / 16;
+    static constexpr int WPB = MT >= NW ? 1 : NW / MT;          // waves per atom block
+    static constexpr int NB = MT >= NW ? MT / NW : 1, CBW = CB / WPB;
+    static constexpr bool ok = T % 16 == 0 && (MT >= NW ? MT % NW == 0 : NW % MT == 0 && CB % WPB == 0);
+};
+
 template <int E, int T, int NW = kOmpWaves>
 __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, int dpad, const float *__restrict__ Xt,
                                                 float *__restrict__ A0, int wave, int lane) {
-    constexpr int Kp = 64 * E, MT = Kp / 16, NB = MT / NW, CB = T / 16;
-    static_assert(T % 16 == 0 && MT % NW == 0 && NB >= 1, "MFMA tile shape");
+    using S = MfmaF32Split<E, T, NW>;
+    constexpr int Kp = 64 * E, MT = S::MT, NB = S::NB, CB = S::CBW;
+    static_assert(S::ok, "MFMA tile shape");
     const int lr = lane & 15, kq = lane >> 4;
+    const int ab0 = MT >= NW ? wave : wave % MT;            // first atom block of this wave
+    const int cb0 = MT >= NW ? 0 : (wave / MT) * CB;        // first column block of this wave
     floatx4 acc[NB][CB];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -181,7 +195,7 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, in
         for (int c = 0; c < CB; ++c) acc[b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
     const float *rowp[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) rowp[b] = Dr + (size_t)((wave + NW * b) * 16 + lr) * dpad + 4 * kq;
+    for (int b = 0; b < NB; ++b) rowp[b] = Dr + (size_t)((ab0 + NW * b) * 16 + lr) * dpad + 4 * kq;
     floatx4 an[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) an[b] = *reinterpret_cast<const floatx4 *>(rowp[b]);
@@ -198,7 +212,7 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, in
             const int f = f0 + 4 * kq + q;
             float bx[CB];
 #pragma unroll
-            for (int c = 0; c < CB; ++c) bx[c] = Xt[f * xt_stride(T) + c * 16 + lr];
+            for (int c = 0; c < CB; ++c) bx[c] = Xt[f * xt_stride(T) + (cb0 + c) * 16 + lr];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -210,7 +224,7 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, in
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-            *reinterpret_cast<floatx4 *>(A0 + (c * 16 + lr) * a0_stride(Kp) + (wave + NW * b) * 16 + 4 * kq) =
+            *reinterpret_cast<floatx4 *>(A0 + ((cb0 + c) * 16 + lr) * a0_stride(Kp) + (ab0 + NW * b) * 16 + 4 * kq) =
                 acc[b][c];
 }
 
@@ -572,11 +586,14 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
     load_tile<T, NW>(p, dict.d, s0, nt, Xt, tid);
     __syncthreads();
     bool done = false;
-    if constexpr (T % 16 == 0) {   // the MFMA stages work on 16-signal column blocks
+    if constexpr (MfmaF32Split<E, T, NW>::ok) {
         if (mode == A0_MFMA_F32) {
             alpha0_mfma_f32<E, T, NW>(dict.Dr, dict.dpad, Xt, A0, wave, lane);
             done = true;
-        } else if (kSplitOK && T == 16 && NW == kOmpWaves && mode == A0_MFMA_BF16X6) {
+        }
+    }
+    if constexpr (kSplitOK && T == 16 && NW == kOmpWaves) {   // BF16 parts of one 16-signal column block
+        if (mode == A0_MFMA_BF16X6) {
             // signal parts [3][T][kXhs]: x = xh + xm + xl in BF16
             uint16_t *Xh = split_in_a0(T, Kp) ? reinterpret_cast<uint16_t *>(A0)
                                               : reinterpret_cast<uint16_t *>(Xt + 64 * xt_stride(T));

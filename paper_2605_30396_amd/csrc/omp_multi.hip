@@ -65,8 +65,16 @@ __device__ __forceinline__ OmpParams scene_params(const SceneDesc &s) {
     return p;
 }
 
+// 16-signal tiles run on 4 waves, 32-signal tiles on 8 (each wave encodes
+// 4 signals of a tile either way; the wider tile halves the dictionary reads
+// per signal of the correlation stage).
+template <int T>
+constexpr int multi_waves() { return T == 32 ? 8 : kOmpWaves; }
+
 template <int T, int RCQ, int MODE>
-__global__ __launch_bounds__(kOmpThreads) void omp_multi_kernel(MultiArgs a) {
+__global__ __launch_bounds__((64 * multi_waves<T>())) __attribute__((amdgpu_waves_per_eu(4)))
+void omp_multi_kernel(MultiArgs a) {
+    constexpr int NW = multi_waves<T>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int64_t tile_sh;
     OmpTally tally;
@@ -100,7 +108,7 @@ __global__ __launch_bounds__(kOmpThreads) void omp_multi_kernel(MultiArgs a) {
         const int nt = (int)min<int64_t>(T, sd.N - s0);
 #define SC_BODY(EI, EE, KK)                                                                            \
     case 4 * EI + KK / 4 - 1:                                                                          \
-        omp_tile<EE, KK, T, false, (EE <= 4 ? RCQ : 0)>(dict, p, MODE, s0, nt, smem_raw, tidv, tally); \
+        omp_tile<EE, KK, T, false, (EE <= 4 ? RCQ : 0), NW>(dict, p, MODE, s0, nt, smem_raw, tidv, tally); \
         break;
         switch (sd.cls) {
             SC_BODY(0, 1, 4) SC_BODY(0, 1, 8) SC_BODY(0, 1, 12) SC_BODY(0, 1, 16)
@@ -146,14 +154,15 @@ static hipError_t launch_multi_t(const MultiArgs &a, int max_kp, int wg_per_cu, 
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kOmpThreads, smem) != hipSuccess ||
+    constexpr int nthreads = 64 * multi_waves<T>();
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, nthreads, smem) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     if (wg_per_cu > 0) per_cu = std::min(per_cu, wg_per_cu);
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(a.total_tiles, (int64_t)multi_cus() * per_cu));
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, st, a.counter);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kOmpThreads), smem, st, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(nthreads), smem, st, a);
     return hipGetLastError();
 }
 
