@@ -25,6 +25,10 @@ CXXFLAGS = [
     "-Wno-unused-result",
     "-Wno-unused-value",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the pursuit's step loop is unrolled over the sparsity cap so that its
+    # per-step arrays stay in registers; at caps 24 and 32 the body exceeds
+    # the default size limit of a forced unroll
+    "-mllvm", "-pragma-unroll-threshold=200000",
 ]
 
 

@@ -294,7 +294,30 @@ __device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)
     }
 }
 
+// v[e] for a wave-uniform slot e (a select chain; for narrow rows).
+template <int E>
+__device__ __forceinline__ float pick_slot(const float (&v)[E], int e) {
+    float r = v[0];
+#pragma unroll
+    for (int q = 1; q < E; ++q) r = e == q ? v[q] : r;
+    return r;
+}
+
 // Encodes signal `sig` (column s of the tile) with one wave.
+//
+// Batch-OMP with alpha = alpha0 - G_I gamma.  The least-squares solve is
+// carried by the inverse Cholesky factor Li = L^-1 of G_II (G_II = L L^T),
+// bordered each time an atom j joins: with g = G[I, j] and w = Li g,
+//   l2 = G_jj - w.w  (the new diagonal of L, squared),
+//   c_j = alpha_j / sqrt(l2)  (alpha_j the current correlation of j),
+//   new row of Li = (-(w^T Li), 1) / sqrt(l2),
+//   gamma += c_j * (new row of Li),   ||r||^2 -= c_j^2,
+// so gamma = Li^T c is current after every step with O(1) work per lane per
+// atom already selected, and no serial substitution.  Lane u holds row u and
+// column u of Li and gamma_u; the broadcasts each step (g, w, the new row,
+// gamma) go through this signal's alpha0 row in LDS, which is free once
+// alpha0 is in registers.  The extreme diagonal values of L decide the FP64
+// refit.
 // RCQ: the Gram rows of the atoms of the first RCQ steps are kept in
 // registers (RCQ * E VGPRs).  The row of the newest atom is fetched as soon
 // as the atom is chosen and held for the next step; older rows are re-read
@@ -303,18 +326,19 @@ __device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)
 // p.resid[sig].
 template <int E, int KMAX, int T, int RCQ>
 __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams &p, int64_t sig, int s,
-                                            const float *__restrict__ Xt, const float *__restrict__ A0, int lane,
+                                            const float *__restrict__ Xt, float *__restrict__ A0, int lane,
                                             int32_t *oidx, float *ocoef, int32_t *ocount, OmpTally &tally) {
     constexpr int Kp = 64 * E;
     constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
     constexpr int kRowBatch = RCQ > 0 ? 1 : (KMAX >= 16 ? 2 : 3);   // within 128 VGPRs (4 waves per SIMD)
+    constexpr int NL = KMAX <= 16 ? 16 : 32;                          // lanes that hold selected atoms
     const int d = dict.d, K = dict.K;
     // k and the lane index are re-read as opaque values per signal, so the
     // per-step tests against them are made where they are used rather than
     // hoisted out of the signal loop (twelve hoisted masks would be spilled)
     int k = p.k;
     asm volatile("" : "+s"(k));
-    int lane_t = lane;   // the lane index for the tests lane < it, likewise opaque
+    int lane_t = lane;   // the lane index for the per-step lane tests, likewise opaque
     asm volatile("" : "+v"(lane_t));
     const float *__restrict__ G = dict.G;
     const float *__restrict__ Dg = dict.D;
@@ -349,37 +373,25 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         const int j = lane * E + e;
         kid[e] = (j < K ? kKeyLive : 0u) | (kKeyIdx - (uint32_t)j);
     }
-    float Lrow[KMAX], Lcol[KMAX];   // lane t: L[t][u] (u < t) and L[u][t] (u > t)
+    // broadcast buffer: [0, 64) gamma, g and the new row of Li, [32, 64) w;
+    // [0, Kp) alpha while the atom is chosen (E >= 4)
+    float *bc = A0 + s * a0_stride(Kp);
+    float LR[KMAX], LC[KMAX];   // lane u: row u and column u of Li (zero past the atoms selected)
 #pragma unroll
     for (int u = 0; u < KMAX; ++u) {
-        Lrow[u] = 0.f;
-        Lcol[u] = 0.f;
+        LR[u] = 0.f;
+        LC[u] = 0.f;
     }
-    float cval = 0.f, linv = 1.f, gam = 0.f;   // lane t: c_t, 1 / L_tt, gamma_t
-    int selv = 0;                               // lane t: atom of step t
+    float gam = 0.f;   // lane t: gamma_t
+    int selv = 0;      // lane t: atom of step t
     float rc[RC > 0 ? RC : 1][E];   // G rows of the atoms of steps t < RC
     float nrow[E];                  // G row of the newest atom (step >= RC)
 #pragma unroll
     for (int e = 0; e < E; ++e) nrow[e] = 0.f;
-    float rr = xx, lmax = 0.f, lmin = 3.4e38f, rr_expl = 0.f;
-    int n = 0, n_gam = 0;   // gamma is current for n_gam atoms
+    float rr = xx, l2max = 0.f, l2min = 3.4e38f, rr_expl = 0.f;
+    int n = 0;
     bool active = xx > 0.f, expl_done = false;
 
-    // gamma = L^-T c for the first nn atoms.  Lane t's accumulator stops
-    // changing once step t is passed (column t of L is zero above the
-    // diagonal), so every lane forms its own gamma_t at the end.
-    auto back_sub = [&](int nn) {
-        float acc = 0.f;
-#pragma unroll
-        for (int t = KMAX - 1; t >= 0; --t) {
-            if (t < nn) {
-                const float gt = readlane_f((cval - acc) * linv, t);
-                acc = fmaf(Lcol[t], gt, acc);
-            }
-        }
-        gam = (cval - acc) * linv;
-        n_gam = nn;
-    };
     // ||x - D_I gamma||^2 with the current gamma (lane i < d holds x_i)
     auto resid2 = [&](int nn) {
         float r = xv;
@@ -417,7 +429,6 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
                 continue;
             }
             if (rr <= eps2 + band) {   // too close to call on the tracked value
-                back_sub(it);
                 const float re = resid2(it);
                 if (re <= eps2) {
                     expl_done = true;
@@ -427,14 +438,13 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
                 }
             }
         }
-        // ---- correlations of the residual and the selection ----
-        if (__builtin_amdgcn_readfirstlane(n_gam) != it) back_sub(it);
+        // ---- correlations of the residual (gamma_t read from bc) and the selection ----
         float al[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) al[e] = a0[e];
 #pragma unroll
         for (int t = 0; t < (it < RC ? it : RC); ++t) {
-            const float gt = readlane_f(gam, t);
+            const float gt = bc[t];
 #pragma unroll
             for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, rc[t][e], al[e]);
         }
@@ -452,7 +462,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 #pragma unroll
             for (int q = 0; q < kRowBatch; ++q) {
                 if (t0 + q < it - 1) {
-                    const float gt = readlane_f(gam, t0 + q);
+                    const float gt = bc[t0 + q];
 #pragma unroll
                     for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[q][e], al[e]);
                 }
@@ -463,15 +473,20 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             for (int t = RC + kRowBatch; t < tend; ++t) {
                 float gr[E];
                 load_row<E>(G + (size_t)readlane_i(selv, t) * Kp + lane * E, gr);
-                const float gt = readlane_f(gam, t);
+                const float gt = bc[t];
 #pragma unroll
                 for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[e], al[e]);
             }
         }
         if (it - 1 >= RC) {
-            const float gt = readlane_f(gam, it - 1);
+            const float gt = bc[it - 1];
 #pragma unroll
             for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, nrow[e], al[e]);
+        }
+        if constexpr (E >= 4) {   // alpha to this signal's LDS row (gamma there is consumed), for alpha_j below
+#pragma unroll
+            for (int e = 0; e < E; e += 4)
+                *reinterpret_cast<floatx4 *>(bc + lane * E + e) = floatx4{al[e], al[e + 1], al[e + 2], al[e + 3]};
         }
         uint32_t best = 0u;
 #pragma unroll
@@ -509,45 +524,55 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             load_row<E>(G + (size_t)j * Kp + lane * E, rc[it < RC ? it : 0]);
         else
             load_row<E>(G + (size_t)j * Kp + lane * E, nrow);
-        // ---- new row of the Cholesky factor: L w = G[I, j] ----
-        const float g = G[(size_t)selv * Kp + j];   // lanes >= it read an unused entry of row 0
-        const float gjj = G[(size_t)j * Kp + j];
-        // lane `it` receives the new row of L
-        float acc = 0.f, wsq = 0.f, wc = 0.f;
-#pragma unroll
-        for (int t = 0; t < it; ++t) {
-            const float wt = readlane_f((g - acc) * linv, t);
-            acc = fmaf(Lrow[t], wt, acc);
-            wsq = fmaf(wt, wt, wsq);
-            wc = fmaf(wt, readlane_f(cval, t), wc);
-            Lrow[t] = writelane_f(wt, it, Lrow[t]);
+        // the signed correlation of atom j, from the lane that holds it
+        const int lj = j / E, ej = j - lj * E;   // owner lane and slot (E need not be a power of 2)
+        float aj;
+        if constexpr (E >= 4) {
+            aj = bc[j];
+        } else {   // a select over E registers and one lane read
+            aj = readlane_f(pick_slot<E>(al, ej), lj);
         }
-        // lane t < it holds w_t (its accumulator is final once step t is
-        // passed, as row t of L is zero right of the diagonal)
-        const float wv = lane_t < it ? (g - acc) * linv : 0.f;
-        const float l2 = gjj - wsq;
+        // ---- new row of Li: w = Li G[I, j], l2 = G_jj - w.w ----
+        const float gjj = G[(size_t)j * Kp + j];
+        float wsum = 0.f, acc = 0.f;
+        if (it > 0) {
+            const float g = lane_t < it ? G[(size_t)selv * Kp + j] : 0.f;   // lane t < it: G[I_t, j]
+            bc[lane] = g;
+            float w = 0.f;
+#pragma unroll
+            for (int t = 0; t < it; ++t) w = fmaf(LR[t], bc[t], w);
+            if (lane < 32) bc[32 + lane] = w;
+            wsum = lanes_sum<NL>(w * w);
+#pragma unroll
+            for (int t = 0; t < it; ++t) acc = fmaf(bc[32 + t], LC[t], acc);   // (w^T Li)_u
+        }
+        const float l2 = gjj - wsum;
         if (!(l2 > 1e-9f * gjj)) {   // numerically dependent on the selected atoms
             active = false;
             continue;
         }
-        const float ell = __builtin_amdgcn_sqrtf(l2);
-        const float inv = __builtin_amdgcn_rcpf(ell);
-        const float zj = A0[s * a0_stride(Kp) + j];
-        const float cn = (zj - wc) * inv;
-        rr = readfirstlane_f(fmaf(-cn, cn, rr));
-        lmax = fmaxf(lmax, ell);
-        lmin = fminf(lmin, ell);
-        Lcol[it] = wv;
-        cval = writelane_f(readfirstlane_f(cn), it, cval);
-        linv = writelane_f(readfirstlane_f(inv), it, linv);
+        const float il = __builtin_amdgcn_rsqf(l2);   // 1 / L_jj
+        const float cj = aj * il;
+        rr = readfirstlane_f(fmaf(-cj, cj, rr));
+        l2max = fmaxf(l2max, l2);
+        l2min = fminf(l2min, l2);
+        const float nu = lane_t == it ? il : -il * acc;   // lane u: Li[it][u] (zero past lane it)
+        if (it > 0) {
+            bc[lane] = nu;
+#pragma unroll
+            for (int u = 0; u < it; ++u) LR[u] = lane_t == it ? bc[u] : LR[u];
+        }
+        LR[it] = lane_t == it ? il : 0.f;
+        LC[it] = nu;
+        gam = fmaf(cj, nu, gam);
+        bc[lane] = gam;
         selv = writelane_i(j, it, selv);
         n = it + 1;
     }
 
     // ---- coefficients, residual, outputs ----
-    if (__builtin_amdgcn_readfirstlane(n_gam) != n) back_sub(n);
     bool refit = false;
-    if (n > 0 && p.fp64_refit) refit = lmax * lmax > p.kappa_max * (lmin * lmin);
+    if (n > 0 && p.fp64_refit) refit = l2max > p.kappa_max * l2min;
     float re = 0.f;
     if (!refit) re = expl_done ? rr_expl : resid2(n);
     if (lane < k) {

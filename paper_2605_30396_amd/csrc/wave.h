@@ -65,6 +65,21 @@ __device__ __forceinline__ float wave_sum(float v) {
     return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
 }
 
+// Sum over lanes [0, NL) (NL a multiple of 16; the other rows are not read).
+template <int NL>
+__device__ __forceinline__ float lanes_sum(float v) {
+    static_assert(NL % 16 == 0 && NL >= 16 && NL <= 64, "whole 16-lane rows");
+    v += dpp_f<SC_DPP_QP1032>(v);
+    v += dpp_f<SC_DPP_QP2301>(v);
+    v += dpp_f<SC_DPP_HMIRROR>(v);
+    v += dpp_f<SC_DPP_MIRROR>(v);
+    float r = readlane_f(v, 0);
+    if constexpr (NL > 16) r += readlane_f(v, 16);
+    if constexpr (NL > 32) r += readlane_f(v, 32);
+    if constexpr (NL > 48) r += readlane_f(v, 48);
+    return r;
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
     // FP64 reduction through 32-bit halves (DPP moves 32 bits)
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
