@@ -361,6 +361,8 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     const float eps2 = eps_abs * eps_abs;
     const float band = 1e-5f * xx;     // FP32 uncertainty of the tracked ||r||^2
     const float brk = 1e-6f * xnorm;   // residual orthogonal to every atom
+    // |alpha| <= brk compared on the bit patterns (both non-negative), in scalar registers
+    const uint32_t brk_bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(brk));
 
     // Key bit 31 marks an atom still selectable: any such key beats every
     // retired or padding atom, whatever their magnitude bits.
@@ -388,7 +390,9 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     float nrow[E];                  // G row of the newest atom (step >= RC)
 #pragma unroll
     for (int e = 0; e < E; ++e) nrow[e] = 0.f;
-    float rr = xx, l2max = 0.f, l2min = 3.4e38f, rr_expl = 0.f;
+    float rr = xx, rr_expl = 0.f;
+    // extreme squared diagonals of L, as bit patterns (every l2 taken is positive)
+    uint32_t l2max = 0u, l2min = 0x7F7FFFFFu;
     int n = 0;
     bool active = xx > 0.f, expl_done = false;
 
@@ -492,7 +496,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 #pragma unroll
         for (int e = 0; e < E; ++e) best = max(best, (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
         uint32_t kb = wave_max_u32(best);
-        if (!(__uint_as_float(kb & kKeyMag) > brk)) {
+        if ((kb & kKeyMag) <= brk_bits) {
             active = false;
             continue;
         }
@@ -513,7 +517,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             for (int e = 0; e < E; ++e)
                 best = max(best, ((dead >> e) & 1u) ? 0u : (__float_as_uint(al[e]) & kKeyMag) | kid[e]);
             kb = wave_max_u32(best);
-            if (!(__uint_as_float(kb & kKeyMag) > brk) || !(kb & kKeyLive)) {
+            if ((kb & kKeyMag) <= brk_bits || !(kb & kKeyLive)) {
                 active = false;
                 continue;
             }
@@ -554,8 +558,8 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         const float il = __builtin_amdgcn_rsqf(l2);   // 1 / L_jj
         const float cj = aj * il;
         rr = readfirstlane_f(fmaf(-cj, cj, rr));
-        l2max = fmaxf(l2max, l2);
-        l2min = fminf(l2min, l2);
+        l2max = max(l2max, __float_as_uint(l2));
+        l2min = min(l2min, __float_as_uint(l2));
         const float nu = lane_t == it ? il : -il * acc;   // lane u: Li[it][u] (zero past lane it)
         if (it > 0) {
             bc[lane] = nu;
@@ -572,7 +576,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 
     // ---- coefficients, residual, outputs ----
     bool refit = false;
-    if (n > 0 && p.fp64_refit) refit = l2max > p.kappa_max * l2min;
+    if (n > 0 && p.fp64_refit) refit = __uint_as_float(l2max) > p.kappa_max * __uint_as_float(l2min);
     float re = 0.f;
     if (!refit) re = expl_done ? rr_expl : resid2(n);
     if (lane < k) {

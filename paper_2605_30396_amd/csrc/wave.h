@@ -1,7 +1,9 @@
 // Wavefront-level primitives for gfx950 (64-lane waves).
 //
-// Reductions use DPP row operations inside each 16-lane row and read the four
-// row results with v_readlane, so the result is wave-uniform.  Every caller
+// Reductions use DPP row operations inside each 16-lane row, then the two
+// row broadcasts (lane 15 of each row into the next, lane 31 into rows 2
+// and 3) so that lane 63 holds the wave's result, read with one v_readlane:
+// the result is wave-uniform and stays in a scalar register.  Every caller
 // must run them with all 64 lanes active.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -42,11 +44,25 @@ __device__ __forceinline__ float readfirstlane_f(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror
+// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror,
+// row_bcast:15, row_bcast:31
 #define SC_DPP_QP1032 0xB1
 #define SC_DPP_QP2301 0x4E
 #define SC_DPP_HMIRROR 0x141
 #define SC_DPP_MIRROR 0x140
+#define SC_DPP_BCAST15 0x142
+#define SC_DPP_BCAST31 0x143
+
+// The row broadcasts: rows not in the row mask receive `idle` (the identity
+// of the reduction).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_bcast_f(float v, float idle) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(idle), __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_bcast_u(uint32_t v, uint32_t idle) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)idle, (int)v, CTRL, ROWS, 0xF, false);
+}
 
 // Max over the wave of non-NaN inputs (callers pass finite values).
 __device__ __forceinline__ float wave_max(float v) {
@@ -54,7 +70,9 @@ __device__ __forceinline__ float wave_max(float v) {
     v = fmaxf(v, dpp_f<SC_DPP_QP2301>(v));
     v = fmaxf(v, dpp_f<SC_DPP_HMIRROR>(v));
     v = fmaxf(v, dpp_f<SC_DPP_MIRROR>(v));
-    return fmaxf(fmaxf(readlane_f(v, 0), readlane_f(v, 16)), fmaxf(readlane_f(v, 32), readlane_f(v, 48)));
+    v = fmaxf(v, dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, v));
+    v = fmaxf(v, dpp_bcast_f<SC_DPP_BCAST31, 0xC>(v, v));
+    return readlane_f(v, 63);
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -62,22 +80,29 @@ __device__ __forceinline__ float wave_sum(float v) {
     v += dpp_f<SC_DPP_QP2301>(v);
     v += dpp_f<SC_DPP_HMIRROR>(v);
     v += dpp_f<SC_DPP_MIRROR>(v);
-    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+    v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, 0.f);
+    v += dpp_bcast_f<SC_DPP_BCAST31, 0xC>(v, 0.f);
+    return readlane_f(v, 63);
 }
 
-// Sum over lanes [0, NL) (NL a multiple of 16; the other rows are not read).
+// Sum over lanes [0, NL) for NL = 16, 32 or 64 (the other rows are not read).
 template <int NL>
 __device__ __forceinline__ float lanes_sum(float v) {
-    static_assert(NL % 16 == 0 && NL >= 16 && NL <= 64, "whole 16-lane rows");
+    static_assert(NL == 16 || NL == 32 || NL == 64, "one, two or four 16-lane rows");
     v += dpp_f<SC_DPP_QP1032>(v);
     v += dpp_f<SC_DPP_QP2301>(v);
     v += dpp_f<SC_DPP_HMIRROR>(v);
     v += dpp_f<SC_DPP_MIRROR>(v);
-    float r = readlane_f(v, 0);
-    if constexpr (NL > 16) r += readlane_f(v, 16);
-    if constexpr (NL > 32) r += readlane_f(v, 32);
-    if constexpr (NL > 48) r += readlane_f(v, 48);
-    return r;
+    if constexpr (NL == 16) {
+        return readlane_f(v, 0);
+    } else if constexpr (NL == 32) {
+        v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, 0.f);
+        return readlane_f(v, 31);
+    } else {
+        v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, 0.f);
+        v += dpp_bcast_f<SC_DPP_BCAST31, 0xC>(v, 0.f);
+        return readlane_f(v, 63);
+    }
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -97,9 +122,9 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     v = max(v, dpp_u<SC_DPP_QP2301>(v));
     v = max(v, dpp_u<SC_DPP_HMIRROR>(v));
     v = max(v, dpp_u<SC_DPP_MIRROR>(v));
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
-    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), e = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-    return max(max(a, b), max(c, e));
+    v = max(v, dpp_bcast_u<SC_DPP_BCAST15, 0xA>(v, 0u));
+    v = max(v, dpp_bcast_u<SC_DPP_BCAST31, 0xC>(v, 0u));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
