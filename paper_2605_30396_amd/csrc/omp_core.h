@@ -378,18 +378,14 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     // broadcast buffer: [0, 64) gamma, g and the new row of Li, [32, 64) w;
     // [0, Kp) alpha while the atom is chosen (E >= 4)
     float *bc = A0 + s * a0_stride(Kp);
-    float LR[KMAX], LC[KMAX];   // lane u: row u and column u of Li (zero past the atoms selected)
-#pragma unroll
-    for (int u = 0; u < KMAX; ++u) {
-        LR[u] = 0.f;
-        LC[u] = 0.f;
-    }
+    // lane u: row u and column u of Li.  Entry t of both is written whole
+    // (every lane) at step t and read only by later steps, so neither needs
+    // clearing; lanes past the atoms selected hold zeros in them.
+    float LR[KMAX], LC[KMAX];
     float gam = 0.f;   // lane t: gamma_t
     int selv = 0;      // lane t: atom of step t
     float rc[RC > 0 ? RC : 1][E];   // G rows of the atoms of steps t < RC
-    float nrow[E];                  // G row of the newest atom (step >= RC)
-#pragma unroll
-    for (int e = 0; e < E; ++e) nrow[e] = 0.f;
+    float nrow[E];                  // G row of the newest atom (step >= RC; loaded before it is read)
     float rr = xx, rr_expl = 0.f;
     // extreme squared diagonals of L, as bit patterns (every l2 taken is positive)
     uint32_t l2max = 0u, l2min = 0x7F7FFFFFu;
