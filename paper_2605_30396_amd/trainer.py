@@ -45,13 +45,19 @@ def train(p: sc.Proposer, X, sup_idx, sup_count, epochs=2, batch=4096, lr=1e-3, 
     return dict(loss=hist, seconds=time.perf_counter() - t0, steps=epochs * nb, batch=batch)
 
 
-def support_recall(p: sc.Proposer, X, sup_idx, sup_count, n_cand=24):
-    """Fraction of signals whose whole OMP support is among the proposer's
-    n_cand candidates (host-side evaluation)."""
-    cand, _ = sc.proposer_forward(p, X, n_cand)
+def candidate_recall(cand, sup_idx, sup_count):
+    """Fraction of signals whose whole OMP support is among their candidate
+    list (cand: N x n_cand device int32, -1 for no candidate)."""
     c = cand.cpu().numpy()
     s = sup_idx.cpu().numpy()
     n = sup_count.cpu().numpy()
     hit = (s[:, :, None] == c[:, None, :]).any(-1)
     valid = np.arange(s.shape[1])[None, :] < n[:, None]
     return float(np.mean(np.all(hit | ~valid, axis=1)))
+
+
+def support_recall(p: sc.Proposer, X, sup_idx, sup_count, n_cand=24):
+    """Fraction of signals whose whole OMP support is among the proposer's
+    n_cand candidates (host-side evaluation)."""
+    cand, _ = sc.proposer_forward(p, X, n_cand)
+    return candidate_recall(cand, sup_idx, sup_count)

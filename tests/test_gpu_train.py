@@ -110,33 +110,57 @@ def test_adam_steps_match_oracle():
     p.destroy()
 
 
-def test_training_gains_over_untrained_network():
-    """A short GPU training run (2000 Adam steps) on 4-sparse signals over a
-    K=512 dictionary: the loss falls, the share of signals whose whole OMP
-    support lies among the 24 candidates rises above the untrained network's
-    (which is ~0), and the learned encoder sends fewer signals to the
-    full-OMP fallback."""
+def test_training_gains_measured_against_screening_and_plain():
+    """A short GPU training run (8192 Adam steps) on 4-sparse signals over a
+    K=512 dictionary, measured on held-out signals against the proposer-free
+    pipelines: screening (top-24 of |D^T x|) feeding the same restricted OMP,
+    and the plain full encoder.  The loss falls and the trained network beats
+    the untrained one (recall@24 of the whole OMP support, fallbacks of the
+    learned encoder).  This network shape trails screening (about 16% recall
+    against 18% once trained to its plateau); the test reports the gap and
+    holds the trained recall to at least 0.6 of screening's.  Codes kept by
+    the restricted stage meet eps; fallback codes are the plain encoder's."""
+    K, k, eps = 512, 12, 1e-2
     D = I.learned_dictionary()
-    Xtr = I.learned_train_signals(D, N=1 << 19)
+    Xtr = I.learned_train_signals(D, N=1 << 21)
     Xte = I.learned_eval_signals(D, N=8192)
+    N = len(Xte)
     h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
     Xtr_g, Xte_g = torch.from_numpy(Xtr).to(DEV), torch.from_numpy(Xte).to(DEV)
-    sup, cnt = trainer.omp_labels(h, Xtr_g, 12, 1e-2)
-    sup_te, cnt_te = trainer.omp_labels(h, Xte_g, 12, 1e-2)
-    p = sc.proposer_create(45, 256, 512)
-    p.set_params(I.mlp_init(I.rng_for(5), 45, 256, 512))
+    sup, cnt = trainer.omp_labels(h, Xtr_g, k, eps)
+    sup_te, cnt_te = trainer.omp_labels(h, Xte_g, k, eps)
+    p = sc.proposer_create(45, 256, K)
+    p.set_params(I.mlp_init(I.rng_for(5), 45, 256, K))
 
-    def fallbacks():
+    def learned():
         sc.omp_stats(h, reset=True)
-        sc.omp_encode_learned(h, p, Xte_g, 12, 1e-2)
-        return sc.omp_stats(h)["fallbacks"]
+        codes = [t.cpu().numpy() for t in sc.omp_encode_learned(h, p, Xte_g, k, eps)]
+        return codes, sc.omp_stats(h)["fallbacks"]
 
-    r0, f0 = trainer.support_recall(p, Xte_g, sup_te, cnt_te), fallbacks()
+    r0, (_, f0) = trainer.support_recall(p, Xte_g, sup_te, cnt_te), learned()
     hist = trainer.train(p, Xtr_g, sup, cnt, epochs=4, batch=1024, lr=3e-3, pos_weight=8.0, seed=312)
-    r1, f1 = trainer.support_recall(p, Xte_g, sup_te, cnt_te), fallbacks()
-    print("recall@24 untrained", r0, "trained", r1, "fallbacks", f0, f1, "loss", hist["loss"], "s", hist["seconds"])
+    r1, (codes, f1) = trainer.support_recall(p, Xte_g, sup_te, cnt_te), learned()
+
+    # proposer-free comparators on the same signals
+    cand_s = sc.screen_topk(h, Xte_g, 24)
+    r_s = trainer.candidate_recall(cand_s, sup_te, cnt_te)
+    h.set_tuning(sc.TUNE_RESTRICTED_CAP, 0)
+    *_, mc = sc.omp_encode_restricted(h, Xte_g, k, eps, cand_s)
+    f_s = int(mc.item())
+    plain = [t.cpu().numpy() for t in sc.omp_encode(h, Xte_g, k, eps)]
+    same = float(np.mean(np.all(codes[0] == plain[0], axis=1)))
+    print(f"recall@24: untrained {r0:.4f} trained {r1:.4f} screening {r_s:.4f} (trained/screening {r1 / r_s:.2f}); "
+          f"fallbacks of {N}: untrained {f0} trained {f1} screening {f_s} plain {N}; "
+          f"codes equal to plain {same:.4f}; loss {hist['loss']}, {hist['seconds']:.1f} s")
     assert hist["loss"][-1] < hist["loss"][0]
     assert r1 > r0 + 0.05
-    assert f1 < f0 - 0.05 * len(Xte)
+    assert f1 < f0 - 0.05 * N
+    assert r1 >= 0.6 * r_s
+    assert f1 <= N and f_s <= N
+    # codes kept by the restricted stage meet eps; the rest are the plain encoder's
+    idx, coef, count, resid = codes
+    kept = resid <= eps * (1 + 1e-6)
+    assert np.all(count[~kept] == plain[2][~kept])
+    np.testing.assert_array_equal(idx[~kept], plain[0][~kept])
     h.destroy()
     p.destroy()
