@@ -78,17 +78,31 @@ struct OmpTally {
 template <int T, int NW = kOmpWaves>
 __device__ __forceinline__ void load_tile(const OmpParams &p, int d, int64_t s0, int nt, float *Xt, int tid) {
     constexpr int NT = 64 * NW;
+    // element f = s d + i of the tile; (s, i) stepped along with f (one
+    // division per thread, not one per element)
+    const int dq = NT / d, dr = NT - dq * d;
+    int s = tid / d, i = tid - (tid / d) * d;
     if (p.rows) {   // a listed row outside [0, N) reads as zeros (and is not encoded)
         for (int f = tid; f < nt * d; f += NT) {
-            const int s = f / d, i = f - s * d;
             const int64_t r = p.rows[s0 + s];
             Xt[i * xt_stride(T) + s] = (uint64_t)r < (uint64_t)p.N ? p.X[r * d + i] : 0.f;
+            s += dq;
+            i += dr;
+            if (i >= d) {
+                i -= d;
+                ++s;
+            }
         }
     } else {
         const float *__restrict__ Xtile = p.X + s0 * d;
         for (int f = tid; f < nt * d; f += NT) {
-            const int s = f / d, i = f - s * d;
             Xt[i * xt_stride(T) + s] = Xtile[f];
+            s += dq;
+            i += dr;
+            if (i >= d) {
+                i -= d;
+                ++s;
+            }
         }
     }
     for (int q = tid; q < 64 * T; q += NT) {
