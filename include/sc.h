@@ -115,9 +115,11 @@ int sc_dict_gram(sc_dict h, float *G_out, void *stream);
  * coefficients on the selected atoms, stop before a selection when the
  * residual norm is <= eps (or eps*||x|| with SC_EPS_RELATIVE) or k atoms are
  * in use.  eps = 0 means "k atoms".  The GPU runs Batch-OMP: correlations
- * alpha0 = D^T x once, then per step an incremental Cholesky row and a
- * Gram-column update of the correlations, and finally a refit of the
- * coefficients from D_I^T x.
+ * alpha0 = D^T x once; per step the Gram-column update
+ * alpha = alpha0 - G_I gamma, the selection, and one new row of the inverse
+ * Cholesky factor L^-1 of G_II (G_II = L L^T), from which the least-squares
+ * coefficients gamma = L^-T L^-1 D_I^T x and the residual norm are updated
+ * in place.
  *
  * Precision (flags): FP32 throughout by default.  SC_PREC_BF16 forms
  * alpha0 = D^T x on BF16 matrix cores with FP32 accumulation: D and x are
@@ -126,10 +128,10 @@ int sc_dict_gram(sc_dict h, float *G_out, void *stream);
  * FP32 (Dm xm + Dl xh + Dh xl + Dm xh + Dh xm + Dh xh).  The products left
  * out and the parts' own rounding add <= 4 * 2^-27 ||x|| per unit atom, so
  * the correlations have the accuracy of FP32 dot products, at half the
- * matrix-core time of FP32 operands.  The Gram-form update, the Cholesky
- * factor, the stop test and the coefficients are FP32 as in the default
- * path.  Supports whose Cholesky condition estimate (max l_ii / min l_ii)^2
- * exceeds 1e3 are refit in FP64 unless SC_NO_FP64_REFIT.
+ * matrix-core time of FP32 operands.  The Gram-form update, the factor,
+ * the stop test and the coefficients are FP32 as in the default path.
+ * Supports whose Cholesky condition estimate (max l_ii / min l_ii)^2 exceeds
+ * 1e3 are refit in FP64 unless SC_NO_FP64_REFIT.
  *
  *   X      device N x d float32          idx   device N x k int32 (out)
  *   N      >= 0 (0: no device work, the  coef  device N x k float32 (out)
@@ -145,8 +147,9 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
  * Tuning of a dictionary handle (chosen by the autotuner; results do not
  * depend on it beyond FP32 rounding order):
  *   SC_TUNE_FP32_CORRELATION  how the FP32 encoder computes alpha0 = D^T x for
- *     a tile of 16 signals: SC_CORR_VALU (FP32 FMAs, default) or SC_CORR_MFMA
- *     (FP32 matrix cores).
+ *     a tile of signals: SC_CORR_VALU (FP32 FMAs over 16-signal tiles,
+ *     default) or SC_CORR_MFMA (FP32 matrix cores; 32-signal tiles on eight
+ *     waves when 64 < K <= 512, else 16-signal tiles).
  *   SC_TUNE_ROW_CACHE  Gram rows of the first selected atoms kept in
  *     registers by the encoder: 0 (default for K > 256: every row re-read
  *     from cache memory when the correlations are formed) or 4 (applies to
