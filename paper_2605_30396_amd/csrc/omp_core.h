@@ -417,7 +417,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int jt = readlane_i(selv, t0 + q);
-                    dv[q] = Dg[(size_t)jt * d + dl];
+                    dv[q] = Dg[(uint32_t)(jt * d + dl)];   // K d < 2^32: 32-bit offsets
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
@@ -550,7 +550,8 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         const float gjj = G[(size_t)j * Kp + j];
         float wsum = 0.f, acc = 0.f;
         if (it > 0) {
-            const float g = lane_t < it ? G[(size_t)selv * Kp + j] : 0.f;   // lane t < it: G[I_t, j]
+            // lane t < it: G[I_t, j] (K Kp < 2^32: a 32-bit offset)
+            const float g = lane_t < it ? G[(uint32_t)(selv * Kp + j)] : 0.f;
             bc[lane] = g;
             float w = 0.f;
 #pragma unroll

@@ -80,8 +80,8 @@ __device__ __forceinline__ float wave_sum(float v) {
     v += dpp_f<SC_DPP_QP2301>(v);
     v += dpp_f<SC_DPP_HMIRROR>(v);
     v += dpp_f<SC_DPP_MIRROR>(v);
-    v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, 0.f);
-    v += dpp_bcast_f<SC_DPP_BCAST31, 0xC>(v, 0.f);
+    v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, -0.f);
+    v += dpp_bcast_f<SC_DPP_BCAST31, 0xC>(v, -0.f);
     return readlane_f(v, 63);
 }
 
@@ -96,11 +96,11 @@ __device__ __forceinline__ float lanes_sum(float v) {
     if constexpr (NL == 16) {
         return readlane_f(v, 0);
     } else if constexpr (NL == 32) {
-        v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, 0.f);
+        v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, -0.f);
         return readlane_f(v, 31);
     } else {
-        v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, 0.f);
-        v += dpp_bcast_f<SC_DPP_BCAST31, 0xC>(v, 0.f);
+        v += dpp_bcast_f<SC_DPP_BCAST15, 0xA>(v, -0.f);
+        v += dpp_bcast_f<SC_DPP_BCAST31, 0xC>(v, -0.f);
         return readlane_f(v, 63);
     }
 }
