@@ -177,8 +177,9 @@ __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d,
 // alpha0 tile on FP32 MFMA (v_mfma_f32_16x16x4_f32): wave w computes the
 // 16-atom blocks w, w+NW, ... for every 16-signal column block; when there
 // are fewer atom blocks than waves, NW / MT waves share an atom block and
-// split the column blocks between them (each output element takes the same
-// MFMA sequence either way, so the values do not depend on the wave count).
+// split the column blocks between them, waves past the last column block
+// staying idle (each output element takes the same MFMA sequence either way,
+// so the values do not depend on the wave count).
 // The contraction runs over 16-feature chunks whose four k-steps take features
 // 4 kq + s (s = 0..3) in lane group kq, so the A operands of a whole chunk are
 // one 16-byte read per lane from the atom-major dictionary Dr (Kp x dpad,
@@ -189,8 +190,10 @@ template <int E, int T, int NW>
 struct MfmaF32Split {
     static constexpr int MT = 16 * E / 4, CB = T / 16;
     static constexpr int WPB = MT >= NW ? 1 : NW / MT;          // waves per atom block
-    static constexpr int NB = MT >= NW ? MT / NW : 1, CBW = CB / WPB;
-    static constexpr bool ok = T % 16 == 0 && (MT >= NW ? MT % NW == 0 : NW % MT == 0 && CB % WPB == 0);
+    static constexpr int NB = MT >= NW ? MT / NW : 1;
+    static constexpr int CBW = CB >= WPB ? CB / WPB : 1;        // column blocks per wave
+    static constexpr bool ok = T % 16 == 0 && (MT >= NW ? MT % NW == 0
+                                                        : NW % MT == 0 && (CB % WPB == 0 || WPB % CB == 0));
 };
 
 template <int E, int T, int NW = kOmpWaves>
@@ -202,6 +205,7 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, in
     const int lr = lane & 15, kq = lane >> 4;
     const int ab0 = MT >= NW ? wave : wave % MT;            // first atom block of this wave
     const int cb0 = MT >= NW ? 0 : (wave / MT) * CB;        // first column block of this wave
+    if (cb0 >= S::CB) return;   // more waves than (atom block, column block) pairs: this one is idle
     floatx4 acc[NB][CB];
 #pragma unroll
     for (int b = 0; b < NB; ++b)

@@ -65,16 +65,17 @@ __device__ __forceinline__ OmpParams scene_params(const SceneDesc &s) {
     return p;
 }
 
-// 16-signal tiles run on 4 waves, 32-signal tiles on 8 (each wave encodes
-// 4 signals of a tile either way; the wider tile halves the dictionary reads
-// per signal of the correlation stage).
-template <int T>
-constexpr int multi_waves() { return T == 32 ? 8 : kOmpWaves; }
+// 32-signal tiles run on 8 waves (the wider tile halves the dictionary reads
+// per signal of the correlation stage), and so do 16-signal tiles with the
+// matrix-core correlation stage (its accumulators then take half the
+// registers per wave); 16-signal tiles with the VALU stage run on 4.
+template <int T, int MODE>
+constexpr int multi_waves() { return (T == 32 || MODE == A0_MFMA_F32) ? 8 : kOmpWaves; }
 
 template <int T, int RCQ, int MODE>
-__global__ __launch_bounds__((64 * multi_waves<T>())) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__((64 * multi_waves<T, MODE>())) __attribute__((amdgpu_waves_per_eu(4)))
 void omp_multi_kernel(MultiArgs a) {
-    constexpr int NW = multi_waves<T>();
+    constexpr int NW = multi_waves<T, MODE>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int64_t tile_sh;
     OmpTally tally;
@@ -154,7 +155,7 @@ static hipError_t launch_multi_t(const MultiArgs &a, int max_kp, int wg_per_cu, 
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    constexpr int nthreads = 64 * multi_waves<T>();
+    constexpr int nthreads = 64 * multi_waves<T, MODE>();
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, nthreads, smem) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;

@@ -46,7 +46,8 @@ SCENES = [(512, 12, 1e-2, 4133), (256, 16, 0.0, 1000), (128, 4, 0.0, 37), (64, 8
 TUNINGS = [None,
            dict(tile=32, row_cache=4, wg_per_cu=1, order=sc.ORDER_GIVEN, corr=sc.CORR_MFMA),
            dict(tile=16, row_cache=4, wg_per_cu=2, order=sc.ORDER_COST, corr=sc.CORR_VALU),
-           dict(tile=32, row_cache=0, wg_per_cu=0, order=sc.ORDER_COST, corr=sc.CORR_MFMA)]
+           dict(tile=32, row_cache=0, wg_per_cu=0, order=sc.ORDER_COST, corr=sc.CORR_MFMA),
+           dict(tile=16, row_cache=4, wg_per_cu=0, order=sc.ORDER_GIVEN, corr=sc.CORR_MFMA)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS)
