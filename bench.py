@@ -446,7 +446,8 @@ def main():
         for _ in range(2):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"quick": True, "ms_per_step": head_ms_step, "phases_ms": ph, "copy_bytes": 1 << 30}))
+        print(json.dumps({"quick": True, "ms_per_step": head_ms_step, "phases_ms": ph, "N": N,
+                          "fallback_rows": fb_rows, "copy_bytes": 1 << 30}))
         return
 
     for name, flags in (("plain_fp32", 0), ("bf16_precision_form", sc.PREC_BF16)):
@@ -588,18 +589,19 @@ def main():
     kern = {
         "proposer": dict(kernel="proposer_topk_kernel", bound="mfma", unit="TFLOP/s", peak=BF16_MFMA_PEAK_TFLOPS,
                          achieved=MLP_FLOPS * N / (phs["proposer"] * 1e-3) / 1e12,
-                         src=("proposer.hip", "mfma.h")),
+                         src=("proposer.hip", "mfma.h", "wave.h", "sc_internal.h")),
         "restricted": dict(kernel="omp_restricted_kernel", bound="alu", unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS,
                            achieved=float(np.sum(2.0 * N_CAND * d + N_CAND * n_ok * (n_ok + 1))) /
-                           (phs["restricted"] * 1e-3) / 1e12, src=("romp.hip",)),
+                           (phs["restricted"] * 1e-3) / 1e12, src=("romp.hip", "wave.h", "sc_internal.h")),
         "fallback": dict(kernel="omp_batch_kernel", bound="alu", unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS,
                          achieved=batch_omp_flops(K, d, cnt_head[miss_np]) / (phs["fallback"] * 1e-3) / 1e12,
-                         src=("omp_core.h", "omp_batch_impl.h")),
+                         src=("omp_core.h", "omp_batch_impl.h", "omp_batch_mfma.hip", "omp_batch_valu.hip", "mfma.h", "wave.h",
+                              "sc_internal.h")),
         "radiance": dict(kernel="sh_eval_kernel", bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
-                         achieved=sh_eval_bytes(N, k) / (eval_ms * 1e-3) / 1e9, src=("sh_eval.hip",)),
+                         achieved=sh_eval_bytes(N, k) / (eval_ms * 1e-3) / 1e9, src=("sh_eval.hip", "sh_basis.h", "sc_internal.h")),
         "radiance_nonzero_bytes": dict(kernel="sh_eval_kernel", bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
                                        achieved=(8 * float(np.maximum(cnt_head, 0).sum()) + 28 * N) /
-                                       (eval_ms * 1e-3) / 1e9, src=("sh_eval.hip",)),
+                                       (eval_ms * 1e-3) / 1e9, src=("sh_eval.hip", "sh_basis.h", "sc_internal.h")),
     }
     for v in kern.values():
         v["frac"] = round(v["achieved"] / v["peak"], 4)

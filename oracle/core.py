@@ -13,7 +13,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sc_oracle.c")
-_SO = os.path.join(_HERE, "libsc_oracle.so")
+# SC_ORACLE_LIB points the wrappers at another build of the same source (the
+# sanitizer build of sanitize_check.sh)
+_SO = os.environ.get("SC_ORACLE_LIB") or os.path.join(_HERE, "libsc_oracle.so")
 _lib = None
 
 
