@@ -350,6 +350,9 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     constexpr int RC = RCQ < KMAX ? RCQ : KMAX;
     constexpr int kRowBatch = RCQ > 0 ? 1 : (KMAX >= 16 ? 2 : 3);   // within 128 VGPRs (4 waves per SIMD)
     constexpr int NL = KMAX <= 16 ? 16 : 32;                          // lanes that hold selected atoms
+    // steps whose broadcasts are lane reads instead of LDS round trips (measured:
+    // faster for the wide rows of K > 256, slower for K <= 256)
+    constexpr int kLaneBcast = E >= 8 ? 4 : 0;
     const int d = dict.d, K = dict.K;
     // k and the lane index are re-read as opaque values per signal, so the
     // per-step tests against them are made where they are used rather than
@@ -460,9 +463,12 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         float al[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) al[e] = a0[e];
+        // gamma_t: from lane t at the first steps (a few lane reads beat an
+        // LDS round trip), from the broadcast row later
+        auto gamma_at = [&](int t) { return it <= kLaneBcast ? readlane_f(gam, t) : bc[t]; };
 #pragma unroll
         for (int t = 0; t < (it < RC ? it : RC); ++t) {
-            const float gt = bc[t];
+            const float gt = gamma_at(t);
 #pragma unroll
             for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, rc[t][e], al[e]);
         }
@@ -480,7 +486,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
 #pragma unroll
             for (int q = 0; q < kRowBatch; ++q) {
                 if (t0 + q < it - 1) {
-                    const float gt = bc[t0 + q];
+                    const float gt = gamma_at(t0 + q);
 #pragma unroll
                     for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[q][e], al[e]);
                 }
@@ -497,7 +503,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             }
         }
         if (it - 1 >= RC) {
-            const float gt = bc[it - 1];
+            const float gt = gamma_at(it - 1);
 #pragma unroll
             for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, nrow[e], al[e]);
         }
@@ -556,14 +562,21 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         if (it > 0) {
             // lane t < it: G[I_t, j] (K Kp < 2^32: a 32-bit offset)
             const float g = lane_t < it ? G[(uint32_t)(selv * Kp + j)] : 0.f;
-            bc[lane] = g;
             float w = 0.f;
+            if (it <= kLaneBcast) {
 #pragma unroll
-            for (int t = 0; t < it; ++t) w = fmaf(LR[t], bc[t], w);
-            if (lane < 32) bc[32 + lane] = w;
+                for (int t = 0; t < it; ++t) w = fmaf(LR[t], readlane_f(g, t), w);
+#pragma unroll
+                for (int t = 0; t < it; ++t) acc = fmaf(readlane_f(w, t), LC[t], acc);   // (w^T Li)_u
+            } else {
+                bc[lane] = g;
+#pragma unroll
+                for (int t = 0; t < it; ++t) w = fmaf(LR[t], bc[t], w);
+                if (lane < 32) bc[32 + lane] = w;
+#pragma unroll
+                for (int t = 0; t < it; ++t) acc = fmaf(bc[32 + t], LC[t], acc);   // (w^T Li)_u
+            }
             wsum = lanes_sum<NL>(w * w);
-#pragma unroll
-            for (int t = 0; t < it; ++t) acc = fmaf(bc[32 + t], LC[t], acc);   // (w^T Li)_u
         }
         const float l2 = gjj - wsum;
         if (!(l2 > 1e-9f * gjj)) {   // numerically dependent on the selected atoms
@@ -576,7 +589,18 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         l2max = max(l2max, __float_as_uint(l2));
         l2min = min(l2min, __float_as_uint(l2));
         const float nu = lane_t == it ? il : -il * acc;   // lane u: Li[it][u] (zero past lane it)
-        if (it > 0) {
+        if (it > 0 && it <= kLaneBcast) {
+            // nu made opaque first: in the select below the compiler would
+            // otherwise read nu's definition under lane == it (nu = il there)
+            // into the lane reads of the other lanes
+            float nu_o = nu;
+            asm volatile("" : "+v"(nu_o));
+#pragma unroll
+            for (int u = 0; u < it; ++u) {
+                const float nv = readlane_f(nu_o, u);
+                LR[u] = lane_t == it ? nv : LR[u];
+            }
+        } else if (it > 0) {
             bc[lane] = nu;
 #pragma unroll
             for (int u = 0; u < it; ++u) LR[u] = lane_t == it ? bc[u] : LR[u];
@@ -584,7 +608,7 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         LR[it] = lane_t == it ? il : 0.f;
         LC[it] = nu;
         gam = fmaf(cj, nu, gam);
-        bc[lane] = gam;
+        if (it + 1 > kLaneBcast) bc[lane] = gam;   // the next step reads gamma from the row
         selv = writelane_i(j, it, selv);
         n = it + 1;
     }
