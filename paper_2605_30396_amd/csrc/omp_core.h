@@ -8,23 +8,24 @@
 //
 //   alpha = alpha0 - G_I gamma                 (correlations of the residual)
 //   j     = argmax_{j not in I} |alpha_j|
-//   w     = L^-1 G[I, j],  l = sqrt(G_jj - |w|^2)      (new row of chol(G_II))
-//   c_n   = (alpha0_j - w . c) / l                     (c = L^-1 alpha0_I)
-//   ||r||^2 -= c_n^2
-//   gamma = L^-T c                                     (back substitution)
+//   w     = Li G[I, j],  l = sqrt(G_jj - |w|^2)       (Li = L^-1, G_II = L L^T)
+//   c_j   = alpha_j / l
+//   new row of Li = (-(w^T Li), 1) / l
+//   gamma += c_j (new row of Li),   ||r||^2 -= c_j^2   (gamma = Li^T c)
 //
 // One 64-lane wave encodes one signal.  Lane l owns atoms l*E .. l*E+E-1
 // (Kp = 64 E) of alpha0; the Gram rows of the selected atoms are re-read
 // (from L2) whenever alpha is formed, so the per-wave register state is
-// O(E + k) and many waves fit on a SIMD.  Lane t keeps step t's scalars
-// (atom, c_t, 1/L_tt, gamma_t), row t of L and column t of L, so both
-// triangular solves run lane-parallel with one v_readlane per step.
+// O(E + k) and several waves fit on a SIMD.  Lane t keeps step t's atom,
+// gamma_t, and row t and column t of Li, so each step costs every lane O(1)
+// per selected atom, with no serial substitution.
 //
 // Selection key: the bits of |alpha_j| with the low 10 mantissa bits replaced
 // by (1023 - j) and bit 31 set while the atom is selectable, so one unsigned
 // wave maximum gives the atom, and entries whose magnitudes agree to 2^-13
-// relative resolve to the lowest index.  Selected and padding atoms have
-// bit 31 clear.
+// relative resolve to the lowest index.  Padding atoms have bit 31 clear;
+// selected atoms keep it (their correlation is zero up to rounding) and are
+// masked only when one of them wins.
 //
 // A support whose Cholesky condition estimate (max L_ii / min L_ii)^2 exceeds
 // kappa_max leaves count = -(2 + n) and the FP32 coefficients; a separate
