@@ -46,10 +46,11 @@ __global__ void dict_check_kernel(const float *__restrict__ D, int d, int K, int
 // DT: d x Kp feature-major; Dbf: Kp x 64 BF16 atom-major, Dlo and Dl2 the
 // BF16 roundings of what the previous parts leave (D = Dbf + Dlo + Dl2 to
 // ~2^-27 relative); D48: K x 48 FP32 atom-major; Dr: Kp x dpad FP32
-// atom-major; all zero padded.
+// atom-major; Dbfo: Dbf in MFMA operand order; all zero padded.
 __global__ void dict_layout_kernel(const float *__restrict__ Dc, int d, int K, int Kp, float *__restrict__ DT,
                                    uint16_t *__restrict__ Dbf, uint16_t *__restrict__ Dlo, uint16_t *__restrict__ Dl2,
-                                   float *__restrict__ D48, float *__restrict__ Dr, int dpad) {
+                                   float *__restrict__ D48, float *__restrict__ Dr, int dpad,
+                                   uint16_t *__restrict__ Dbfo) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= Kp * 64) return;
     int j = t / 64, i = t % 64;   // atom, feature
@@ -58,6 +59,7 @@ __global__ void dict_layout_kernel(const float *__restrict__ Dc, int d, int K, i
     const float r1 = v - __uint_as_float((uint32_t)hi << 16);
     const uint16_t mid = f32_to_bf16(r1);
     Dbf[t] = hi;
+    Dbfo[op_order_index(j, i, 64)] = hi;
     Dlo[t] = mid;
     Dl2[t] = f32_to_bf16(r1 - __uint_as_float((uint32_t)mid << 16));
     if (i < d) DT[(size_t)i * Kp + j] = v;
@@ -91,9 +93,9 @@ hipError_t launch_dict_check(const float *D, int d, int K, int normalize, float 
 }
 
 hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *DT, uint16_t *Dbf, uint16_t *Dlo,
-                               uint16_t *Dl2, float *D48, float *Dr, int dpad, hipStream_t st) {
+                               uint16_t *Dl2, float *D48, float *Dr, int dpad, uint16_t *Dbfo, hipStream_t st) {
     int n = Kp * 64;
-    dict_layout_kernel<<<(n + 255) / 256, 256, 0, st>>>(Dcopy, d, K, Kp, DT, Dbf, Dlo, Dl2, D48, Dr, dpad);
+    dict_layout_kernel<<<(n + 255) / 256, 256, 0, st>>>(Dcopy, d, K, Kp, DT, Dbf, Dlo, Dl2, D48, Dr, dpad, Dbfo);
     return hipGetLastError();
 }
 

@@ -7,7 +7,10 @@
 // of the weight matrix read from global memory (L2-resident), the B operand
 // comes from the activation tile in LDS.  Each wave owns whole 32-row blocks
 // of W for both 32-signal halves of the tile, so every weight is read once
-// per tile, and the A operands are prefetched several k-steps ahead.  In the
+// per tile.  The weights are stored in MFMA operand order (the 64 lanes' 16-byte
+// pieces of one block and k-step are 1 KB contiguous), so an A-operand read is
+// eight whole cache lines instead of 32 partial ones, and the A operands are
+// kept 8 (layers 1-2) or 3 (layer 3) k-steps ahead, the B operands one.  In the
 // MFMA output layout a lane holds 16 outputs of one signal per block, so the
 // selection needs no transpose:
 //   1. each lane takes maxima of groups of K/64 of its logits: 64 group
@@ -42,7 +45,9 @@ constexpr int kXS = 72;        // LDS row stride (bf16) of the input tile
 constexpr int kHS = 264;       // LDS row stride (bf16) of a hidden tile
 constexpr int kNG = 64;        // group maxima per signal
 constexpr int kRankPer = 8;    // survivors ranked per selection lane (rank path: <= 64 per signal)
-constexpr int kThetaLowBit = 11;   // lowest key bit the threshold search resolves
+constexpr int kThetaLowBit = 15;   // lowest key bit the threshold search resolves
+constexpr int kPFHidden = 8;       // A-operand k-steps in flight, hidden layers
+constexpr int kPFOut = 3;          // A-operand k-steps in flight, output layer
 
 constexpr int kXBytes = kPT * kXS * 2;        //  9216
 constexpr int kHBytes = kPT * kHS * 2;        // 33792
@@ -70,25 +75,43 @@ __device__ __forceinline__ uint32_t grp8_max(uint32_t v) {
     return v;
 }
 
+// A operand of 32-row block mb, k-step s, for this lane, from a weight matrix
+// of ldw columns stored in MFMA operand order: block-major, then k-step, then
+// the 64 lanes' 8 consecutive BF16 values (row 32 mb + lane % 32, columns
+// 16 s + 8 (lane / 32) .. + 7).
+__device__ __forceinline__ bf16x8 ld_a_op(const uint16_t *W, int ldw, int mb, int s, int lane) {
+    return ld_bf16x8(W + (((size_t)mb * (ldw / 16) + s) * 64 + lane) * 8);
+}
+
 // One hidden layer for the 64-signal tile: Hout = GELU(W Hin^T + b)^T (BF16),
-// 256 outputs.  Wave w computes the 32-neuron block w for both signal halves;
-// all KS = kin / 16 A operands of the block are loaded up front.
+// 256 outputs.  Wave w computes the 32-neuron block w for both signal halves.
+// Each k-step group (next B operands, two MFMAs, the A operand kPFHidden
+// steps ahead) is fenced from the scheduler, which otherwise sinks the loads
+// to their first use.
 template <int KS>
 __device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int ldw,
                                             const float *__restrict__ bias, const uint16_t *__restrict__ Hin, int ldh,
                                             uint16_t *__restrict__ Hout, int wave, int lane) {
     const int lr = lane & 31, lk = 8 * (lane >> 5);
-    bf16x8 a[KS];
+    constexpr int PF = KS < kPFHidden ? KS : kPFHidden;
+    bf16x8 a[PF];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) a[s] = ld_bf16x8(W + (size_t)(32 * wave + lr) * ldw + 16 * s + lk);
+    for (int s = 0; s < PF; ++s) a[s] = ld_a_op(W, ldw, wave, s, lane);
+    bf16x8 b[2][2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) b[0][n] = ld_bf16x8(Hin + (32 * n + lr) * ldh + lk);
     floatx16 acc[2] = {floatx16{}, floatx16{}};
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
+        if (s + 1 < KS) {
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
-            const bf16x8 b = ld_bf16x8(Hin + (32 * n + lr) * ldh + 16 * s + lk);
-            acc[n] = mfma32(a[s], b, acc[n]);
+            for (int n = 0; n < 2; ++n) b[(s + 1) & 1][n] = ld_bf16x8(Hin + (32 * n + lr) * ldh + 16 * (s + 1) + lk);
         }
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[n] = mfma32(a[s % PF], b[s & 1][n], acc[n]);
+        if (s + PF < KS) a[s % PF] = ld_a_op(W, ldw, wave, s + PF, lane);
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int n = 0; n < 2; ++n) {
@@ -208,26 +231,32 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
             for (int n = 0; n < NPW; ++n) acc[q][n] = floatx16{};
         {
-            constexpr int PF = MPW > 1 ? 2 : 4;   // k-steps of A operands in flight
+            constexpr int PF = kPFOut;
             bf16x8 a[PF][MPW];
 #pragma unroll
             for (int s = 0; s < PF; ++s)
 #pragma unroll
-                for (int q = 0; q < MPW; ++q)
-                    a[s][q] = ld_bf16x8(P.W3b + (size_t)(32 * mblk(q) + lr) * KIN + 16 * s + lk);
+                for (int q = 0; q < MPW; ++q) a[s][q] = ld_a_op(P.W3b, KIN, mblk(q), s, lane);
+            bf16x8 b[2][NPW];
+#pragma unroll
+            for (int n = 0; n < NPW; ++n) b[0][n] = ld_bf16x8(Hin + (32 * (n0 + n) + lr) * LDH + lk);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int s = 0; s < KIN / 16; ++s) {
+                if (s + 1 < KIN / 16) {
 #pragma unroll
-                for (int n = 0; n < NPW; ++n) {
-                    const bf16x8 b = ld_bf16x8(Hin + (32 * (n0 + n) + lr) * LDH + 16 * s + lk);
-#pragma unroll
-                    for (int q = 0; q < MPW; ++q) acc[q][n] = mfma32(a[s % PF][q], b, acc[q][n]);
+                    for (int n = 0; n < NPW; ++n)
+                        b[(s + 1) & 1][n] = ld_bf16x8(Hin + (32 * (n0 + n) + lr) * LDH + 16 * (s + 1) + lk);
                 }
+#pragma unroll
+                for (int n = 0; n < NPW; ++n)
+#pragma unroll
+                    for (int q = 0; q < MPW; ++q) acc[q][n] = mfma32(a[s % PF][q], b[s & 1][n], acc[q][n]);
                 if (s + PF < KIN / 16) {
 #pragma unroll
-                    for (int q = 0; q < MPW; ++q)
-                        a[s % PF][q] = ld_bf16x8(P.W3b + (size_t)(32 * mblk(q) + lr) * KIN + 16 * (s + PF) + lk);
+                    for (int q = 0; q < MPW; ++q) a[s % PF][q] = ld_a_op(P.W3b, KIN, mblk(q), s + PF, lane);
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         __syncthreads();   // every wave is done reading the layer-3 input before the scratch overlays it
@@ -291,7 +320,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             const int hbw = (int)wave_max_u32((uint32_t)(hb + 1)) - 1;
             // largest tau with >= n_cand maxima at or above it, resolved down to
             // bit kThetaLowBit (the low mantissa bits left at zero only lower
-            // tau by < 2^-12 relative: a still-safe bound, at most a few more
+            // tau by < 2^-8 relative: a still-safe bound, at most a few more
             // survivors, and fewer search steps)
             for (int bit = hbw; bit >= kThetaLowBit; --bit) {
                 const uint32_t t2 = tau | (1u << bit);
@@ -466,12 +495,15 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     }
 }
 
-// FP32 master parameters -> BF16 MFMA copies (W1 padded to 64 inputs), plus
-// transposed BF16 copies of W2 and W3 for the backward products of training
-// (their reduction index is then contiguous).
+// FP32 master parameters -> BF16 copies: row-major W1 (padded to 64 inputs),
+// W2, W3 and transposed W2, W3 for the training products (their reduction
+// index is then contiguous), and W1, W2, W3 in MFMA operand order for the
+// inference kernel.
 __global__ void proposer_pack_kernel(const float *__restrict__ params, int d, int H, int K, uint16_t *__restrict__ W1b,
                                      uint16_t *__restrict__ W2b, uint16_t *__restrict__ W3b,
-                                     uint16_t *__restrict__ W2bT, uint16_t *__restrict__ W3bT) {
+                                     uint16_t *__restrict__ W2bT, uint16_t *__restrict__ W3bT,
+                                     uint16_t *__restrict__ W1o, uint16_t *__restrict__ W2o,
+                                     uint16_t *__restrict__ W3o) {
     const int64_t n1 = (int64_t)H * 64, n2 = (int64_t)H * H, n3 = (int64_t)K * H;
     const float *W1 = params;
     const float *W2 = W1 + (size_t)H * d + H;
@@ -479,12 +511,20 @@ __global__ void proposer_pack_kernel(const float *__restrict__ params, int d, in
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n1 + 2 * (n2 + n3);
          t += (int64_t)gridDim.x * blockDim.x) {
         if (t < n1) {
-            int i = (int)(t / 64), f = (int)(t % 64);
-            W1b[t] = bf16_bits(f < d ? W1[(size_t)i * d + f] : 0.f);
+            const int i = (int)(t / 64), f = (int)(t % 64);
+            const uint16_t v = bf16_bits(f < d ? W1[(size_t)i * d + f] : 0.f);
+            W1b[t] = v;
+            W1o[op_order_index(i, f, 64)] = v;
         } else if (t < n1 + n2) {
-            W2b[t - n1] = bf16_bits(W2[t - n1]);
+            const int64_t q = t - n1;
+            const uint16_t v = bf16_bits(W2[q]);
+            W2b[q] = v;
+            W2o[op_order_index((int)(q / H), (int)(q % H), H)] = v;
         } else if (t < n1 + n2 + n3) {
-            W3b[t - n1 - n2] = bf16_bits(W3[t - n1 - n2]);
+            const int64_t q = t - n1 - n2;
+            const uint16_t v = bf16_bits(W3[q]);
+            W3b[q] = v;
+            W3o[op_order_index((int)(q / H), (int)(q % H), H)] = v;
         } else if (t < n1 + 2 * n2 + n3) {
             const int64_t q = t - n1 - n2 - n3;   // W2bT[j][i] = W2[i][j]
             const int64_t j = q / H, i = q - j * H;
@@ -498,8 +538,10 @@ __global__ void proposer_pack_kernel(const float *__restrict__ params, int d, in
 }
 
 hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16_t *W1b, uint16_t *W2b,
-                                uint16_t *W3b, uint16_t *W2bT, uint16_t *W3bT, hipStream_t st) {
-    proposer_pack_kernel<<<1024, 256, 0, st>>>(params, d, H, K, W1b, W2b, W3b, W2bT, W3bT);
+                                uint16_t *W3b, uint16_t *W2bT, uint16_t *W3bT, uint16_t *W1o, uint16_t *W2o,
+                                uint16_t *W3o, hipStream_t st) {
+    if (H % 32 != 0 || K % 32 != 0) return hipErrorInvalidValue;
+    proposer_pack_kernel<<<1024, 256, 0, st>>>(params, d, H, K, W1b, W2b, W3b, W2bT, W3bT, W1o, W2o, W3o);
     return hipGetLastError();
 }
 
@@ -534,11 +576,12 @@ hipError_t launch_proposer_topk(const PropDev &P, const float *X, int64_t N, int
 }
 
 // Correlation screening: the n_cand atoms of largest |<a_j, x>| by one BF16
-// MFMA product with the dictionary's BF16 copy Dbf (Kp x 64, features padded).
-hipError_t launch_screen_topk(const uint16_t *Dbf, int d, int K, const float *X, int64_t N, int n_cand,
+// MFMA product with the dictionary's BF16 copy in MFMA operand order (Kp x 64,
+// features padded).
+hipError_t launch_screen_topk(const uint16_t *Dbfo, int d, int K, const float *X, int64_t N, int n_cand,
                               int32_t *cand, hipStream_t st) {
     if (d > 64 || n_cand < 1 || n_cand > kNG) return hipErrorInvalidValue;
-    PropDev P{d, kPH, K, nullptr, nullptr, nullptr, nullptr, Dbf, nullptr};
+    PropDev P{d, kPH, K, nullptr, nullptr, nullptr, nullptr, Dbfo, nullptr};
     switch (K) {
         case 128: return launch_topk_t<1, true>(P, X, N, n_cand, cand, nullptr, st);
         case 256: return launch_topk_t<2, true>(P, X, N, n_cand, cand, nullptr, st);

@@ -51,6 +51,7 @@ void free_dict(sc_dict h) {
     hipFree(h->DT);
     hipFree(h->G);
     hipFree(h->Dbf);
+    hipFree(h->Dbfo);
     hipFree(h->Dlo);
     hipFree(h->Dl2);
     hipFree(h->Dr);
@@ -103,6 +104,7 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
               hipMalloc(&h->DT, sizeof(float) * (size_t)sc::dt_rows(d) * Kp) == hipSuccess &&
               hipMalloc(&h->G, sizeof(float) * (size_t)K * Kp) == hipSuccess &&
               hipMalloc(&h->Dbf, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
+              hipMalloc(&h->Dbfo, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->Dlo, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->Dl2, sizeof(uint16_t) * (size_t)Kp * 64) == hipSuccess &&
               hipMalloc(&h->Dr, sizeof(float) * (size_t)Kp * dpad) == hipSuccess &&
@@ -134,7 +136,8 @@ int sc_gram_precompute(const float *D, int d, int K, int flags, void *stream, sc
         return SC_ENORM;
     }
     if ((e = hipMemsetAsync(h->DT, 0, sizeof(float) * (size_t)sc::dt_rows(d) * Kp, st)) != hipSuccess ||
-        (e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->Dl2, h->D48, h->Dr, dpad, st)) != hipSuccess ||
+        (e = sc::launch_dict_layouts(h->D, d, K, Kp, h->DT, h->Dbf, h->Dlo, h->Dl2, h->D48, h->Dr, dpad, h->Dbfo,
+                                     st)) != hipSuccess ||
         (e = sc::launch_gram(h->D, d, K, Kp, h->G, h->G64, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         free_dict(h);
@@ -419,6 +422,9 @@ static void free_proposer(sc_proposer p) {
     hipFree(p->W3b);
     hipFree(p->W2bT);
     hipFree(p->W3bT);
+    hipFree(p->W1o);
+    hipFree(p->W2o);
+    hipFree(p->W3o);
     delete p;
 }
 
@@ -439,7 +445,10 @@ int sc_proposer_create(int d, int H, int K, sc_proposer *out) {
               hipMalloc(&p->W2b, sizeof(uint16_t) * (size_t)H * H) == hipSuccess &&
               hipMalloc(&p->W3b, sizeof(uint16_t) * (size_t)K * H) == hipSuccess &&
               hipMalloc(&p->W2bT, sizeof(uint16_t) * (size_t)H * H) == hipSuccess &&
-              hipMalloc(&p->W3bT, sizeof(uint16_t) * (size_t)K * H) == hipSuccess;
+              hipMalloc(&p->W3bT, sizeof(uint16_t) * (size_t)K * H) == hipSuccess &&
+              hipMalloc(&p->W1o, sizeof(uint16_t) * (size_t)H * 64) == hipSuccess &&
+              hipMalloc(&p->W2o, sizeof(uint16_t) * (size_t)H * H) == hipSuccess &&
+              hipMalloc(&p->W3o, sizeof(uint16_t) * (size_t)K * H) == hipSuccess;
     if (!ok ||
         hipMemset(p->params, 0, pb) != hipSuccess || hipMemset(p->m, 0, pb) != hipSuccess ||
         hipMemset(p->v, 0, pb) != hipSuccess || hipMemset(p->grads, 0, pb) != hipSuccess) {
@@ -475,7 +484,8 @@ int sc_proposer_set_params(sc_proposer p, const float *params, void *stream) {
     SC_HIP(hipMemsetAsync(p->m, 0, pb, st), "sc_proposer_set_params");
     SC_HIP(hipMemsetAsync(p->v, 0, pb, st), "sc_proposer_set_params");
     p->step = 0;
-    SC_HIP(sc::launch_proposer_pack(p->params, p->d, p->H, p->K, p->W1b, p->W2b, p->W3b, p->W2bT, p->W3bT, st),
+    SC_HIP(sc::launch_proposer_pack(p->params, p->d, p->H, p->K, p->W1b, p->W2b, p->W3b, p->W2bT, p->W3bT, p->W1o,
+                                    p->W2o, p->W3o, st),
            "sc_proposer_set_params");
     return SC_OK;
 }
@@ -504,7 +514,7 @@ int sc_screen_topk(sc_dict h, const float *X, int64_t N, int n_cand, int32_t *ca
     if (K != 128 && K != 256 && K != 512) return SC_EINVAL;
     if (N == 0) return SC_OK;
     if (!X || !cand) return SC_EINVAL;
-    hipError_t e = sc::launch_screen_topk(h->Dbf, h->dev.d, K, X, N, n_cand, cand, (hipStream_t)stream);
+    hipError_t e = sc::launch_screen_topk(h->Dbfo, h->dev.d, K, X, N, n_cand, cand, (hipStream_t)stream);
     if (e != hipSuccess) return set_dev_error("sc_screen_topk", e);
     return SC_OK;
 }
@@ -912,7 +922,9 @@ int sc_proposer_train_step(sc_proposer p, const float *X, const int32_t *rows, i
         const float lr_t = (float)(lr * sqrt(bc2) / bc1);
         const float eps_hat = (float)(adam_eps * sqrt(bc2));
         SC_HIP(sc::launch_adam(p->params, p->m, p->v, p->grads, p->nparams, lr_t, beta1, beta2, eps_hat, st), fn);
-        SC_HIP(sc::launch_proposer_pack(p->params, d, H, K, p->W1b, p->W2b, p->W3b, p->W2bT, p->W3bT, st), fn);
+        SC_HIP(sc::launch_proposer_pack(p->params, d, H, K, p->W1b, p->W2b, p->W3b, p->W2bT, p->W3bT, p->W1o, p->W2o,
+                                        p->W3o, st),
+               fn);
     }
     return SC_OK;
 }

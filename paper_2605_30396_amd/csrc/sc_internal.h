@@ -30,6 +30,14 @@ inline int pick_kmax(int k) {
 // further k-step of 4 zero rows (the correlation stage reads a k-step ahead).
 inline int dt_rows(int d) { return ((d + 3) & ~3) + 4; }
 
+// Position of element (i, f) of a row-major matrix of C columns (C a multiple
+// of 16, rows a multiple of 32) in MFMA operand order: the A operand of
+// v_mfma_f32_32x32x16_bf16 for 32-row block i / 32 and k-step f / 16 is 64
+// lanes x 8 consecutive values, lane = 32 ((f / 8) % 2) + i % 32.
+__host__ __device__ inline size_t op_order_index(int i, int f, int C) {
+    return ((((size_t)(i >> 5) * (C >> 4) + (f >> 4)) * 64 + 32 * ((f >> 3) & 1) + (i & 31)) << 3) + (f & 7);
+}
+
 struct DictDev {
     int d, K, Kp, E;
     const float *D;    // K x d atom-major FP32
@@ -86,11 +94,13 @@ struct RompParams {
 
 struct PropDev {
     int d, H, K;
-    const uint16_t *W1b;   // H x 64 BF16 (inputs zero padded)
+    // The weight copies read by the inference kernel are in MFMA operand order
+    // (op_order_index below): W1 H x 64 (inputs zero padded), W2 H x H, W3 K x H.
+    const uint16_t *W1b;
     const float *b1;
-    const uint16_t *W2b;   // H x H BF16
+    const uint16_t *W2b;
     const float *b2;
-    const uint16_t *W3b;   // K x H BF16
+    const uint16_t *W3b;
     const float *b3;
 };
 
@@ -98,7 +108,7 @@ struct PropDev {
 hipError_t launch_dict_check(const float *D, int d, int K, int normalize, float *Dcopy, int *status,
                              hipStream_t st);
 hipError_t launch_dict_layouts(const float *Dcopy, int d, int K, int Kp, float *DT, uint16_t *Dbf, uint16_t *Dlo,
-                               uint16_t *Dl2, float *D48, float *Dr, int dpad, hipStream_t st);
+                               uint16_t *Dl2, float *D48, float *Dr, int dpad, uint16_t *Dbfo, hipStream_t st);
 hipError_t launch_gram(const float *Dcopy, int d, int K, int Kp, float *G, double *G64, hipStream_t st);
 hipError_t launch_omp_batch(const DictDev &dict, const OmpParams &p, int kmax, int a0mode, int row_cache,
                             hipStream_t st);
@@ -117,8 +127,9 @@ hipError_t launch_omp_multi(const sc_scene *scenes, const int *order, int n, int
 hipError_t launch_omp_restricted(const DictDev &dict, const float *D48, const RompParams &p, int kmax,
                                  hipStream_t st);
 hipError_t launch_proposer_pack(const float *params, int d, int H, int K, uint16_t *W1b, uint16_t *W2b,
-                                uint16_t *W3b, uint16_t *W2bT, uint16_t *W3bT, hipStream_t st);
-hipError_t launch_screen_topk(const uint16_t *Dbf, int d, int K, const float *X, int64_t N, int n_cand,
+                                uint16_t *W3b, uint16_t *W2bT, uint16_t *W3bT, uint16_t *W1o, uint16_t *W2o,
+                                uint16_t *W3o, hipStream_t st);
+hipError_t launch_screen_topk(const uint16_t *Dbfo, int d, int K, const float *X, int64_t N, int n_cand,
                               int32_t *cand, hipStream_t st);
 hipError_t launch_proposer_topk(const PropDev &P, const float *X, int64_t N, int n_cand, int32_t *cand,
                                 float *logits, hipStream_t st);
@@ -181,6 +192,7 @@ struct sc_dict_s {
     float *DT = nullptr;
     float *G = nullptr;
     uint16_t *Dbf = nullptr;
+    uint16_t *Dbfo = nullptr;   // Dbf in MFMA operand order (the screening product)
     uint16_t *Dlo = nullptr;
     uint16_t *Dl2 = nullptr;
     float *Dr = nullptr;    // Kp x dpad FP32 atom-major (MFMA operands)
@@ -204,11 +216,12 @@ struct sc_proposer_s {
     float *grads = nullptr;      // gradient buffer (same layout)
     uint16_t *W1b = nullptr, *W2b = nullptr, *W3b = nullptr;
     uint16_t *W2bT = nullptr, *W3bT = nullptr;   // transposed copies for the backward products
+    uint16_t *W1o = nullptr, *W2o = nullptr, *W3o = nullptr;   // MFMA operand-order copies (inference)
     int64_t step = 0;
     sc::PropDev dev() const {
         const float *b1 = params + (size_t)H * d;
         const float *b2 = b1 + H + (size_t)H * H;
         const float *b3 = b2 + H + (size_t)K * H;
-        return sc::PropDev{d, H, K, W1b, b1, W2b, b2, W3b, b3};
+        return sc::PropDev{d, H, K, W1o, b1, W2o, b2, W3o, b3};
     }
 };
