@@ -410,25 +410,43 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
-                // one survivor per pass (entries g, g + 8, ...): count the list
-                // entries above it, four at a time
+                // the list is zero-filled up to a multiple of 16 entries (0 is
+                // below every key, so no entry bound is needed); each lane ranks
+                // its own survivors g, g + 8, ... against the whole list, 16
+                // entries (four 16-byte reads in flight) at a time
+                const int nrnd = (int)((maxS + 15u) & ~15u);
+                for (int u = hv + g; u < nrnd; u += 8) lst[u] = 0u;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                uint32_t v[kRankPer];
+                int r[kRankPer];
 #pragma unroll
                 for (int i = 0; i < kRankPer; ++i) {
-                    if ((uint32_t)(8 * i) < maxS) {
-                        const int q = g + 8 * i;
-                        const uint32_t v = q < hv ? lst[q] : 0u;
-                        int r = 0;
-                        for (uint32_t u = 0; u < maxS; u += 4) {
-                            const uint4 x = *reinterpret_cast<const uint4 *>(lst + u);
-                            r += ((int)u < hv && x.x > v) ? 1 : 0;
-                            r += ((int)u + 1 < hv && x.y > v) ? 1 : 0;
-                            r += ((int)u + 2 < hv && x.z > v) ? 1 : 0;
-                            r += ((int)u + 3 < hv && x.w > v) ? 1 : 0;
+                    const int q = g + 8 * i;
+                    v[i] = ((uint32_t)(8 * i) < maxS && q < hv) ? lst[q] : 0u;
+                    r[i] = 0;
+                }
+                for (int u0 = 0; u0 < nrnd; u0 += 16) {
+                    uint4 x[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) x[c] = *reinterpret_cast<const uint4 *>(lst + u0 + 4 * c);
+#pragma unroll
+                    for (int i = 0; i < kRankPer; ++i) {
+                        if ((uint32_t)(8 * i) < maxS) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                r[i] += (x[c].x > v[i] ? 1 : 0) + (x[c].y > v[i] ? 1 : 0) + (x[c].z > v[i] ? 1 : 0) +
+                                        (x[c].w > v[i] ? 1 : 0);
                         }
-                        if (q < hv && r < n_cand) {
-                            const uint32_t at = IMASK - (v & IMASK);
-                            atomicOr(&mw[at >> 5], 1u << (at & 31));
-                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kRankPer; ++i) {
+                    const int q = g + 8 * i;
+                    if ((uint32_t)(8 * i) < maxS && q < hv && r[i] < n_cand) {
+                        const uint32_t at = IMASK - (v[i] & IMASK);
+                        atomicOr(&mw[at >> 5], 1u << (at & 31));
                     }
                 }
             } else {
