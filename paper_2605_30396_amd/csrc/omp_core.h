@@ -75,37 +75,55 @@ struct OmpTally {
 };
 
 // Signals s0 .. s0+nt-1 of the call (through `rows` when given), stored
-// feature-major Xt[i][s]; features >= d and columns >= nt are zero.
+// feature-major Xt[i][s]; features >= d and columns >= nt are zero.  A thread
+// holds at most NE = T * 64 / NT elements of the tile (d <= 64); all of its
+// loads (the listed row numbers first, then the signal entries) are issued
+// from clamped addresses before any is used, so the tile costs one or two
+// memory round trips instead of one or two per element.
 template <int T, int NW = kOmpWaves>
 __device__ __forceinline__ void load_tile(const OmpParams &p, int d, int64_t s0, int nt, float *Xt, int tid) {
     constexpr int NT = 64 * NW;
+    constexpr int NE = (T * 64 + NT - 1) / NT;
     // element f = s d + i of the tile; (s, i) stepped along with f (one
     // division per thread, not one per element)
     const int dq = NT / d, dr = NT - dq * d;
     int s = tid / d, i = tid - (tid / d) * d;
+    int se[NE], ie[NE];
+    bool ok[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        ok[e] = tid + e * NT < nt * d;
+        se[e] = ok[e] ? s : 0;
+        ie[e] = ok[e] ? i : 0;
+        s += dq;
+        i += dr;
+        if (i >= d) {
+            i -= d;
+            ++s;
+        }
+    }
+    float v[NE];
     if (p.rows) {   // a listed row outside [0, N) reads as zeros (and is not encoded)
-        for (int f = tid; f < nt * d; f += NT) {
-            const int64_t r = p.rows[s0 + s];
-            Xt[i * xt_stride(T) + s] = (uint64_t)r < (uint64_t)p.N ? p.X[r * d + i] : 0.f;
-            s += dq;
-            i += dr;
-            if (i >= d) {
-                i -= d;
-                ++s;
-            }
+        int64_t r[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) r[e] = p.rows[s0 + se[e]];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const bool in = ok[e] && (uint64_t)r[e] < (uint64_t)p.N;
+            v[e] = p.X[(in ? r[e] : 0) * d + ie[e]];
+            v[e] = in ? v[e] : 0.f;
         }
     } else {
         const float *__restrict__ Xtile = p.X + s0 * d;
-        for (int f = tid; f < nt * d; f += NT) {
-            Xt[i * xt_stride(T) + s] = Xtile[f];
-            s += dq;
-            i += dr;
-            if (i >= d) {
-                i -= d;
-                ++s;
-            }
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            v[e] = Xtile[ok[e] ? tid + e * NT : 0];
+            v[e] = ok[e] ? v[e] : 0.f;
         }
     }
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+        if (ok[e]) Xt[ie[e] * xt_stride(T) + se[e]] = v[e];
     for (int q = tid; q < 64 * T; q += NT) {
         const int i = q / T, s = q - i * T;
         if (i >= d || s >= nt) Xt[i * xt_stride(T) + s] = 0.f;

@@ -45,7 +45,7 @@ constexpr int kXS = 72;        // LDS row stride (bf16) of the input tile
 constexpr int kHS = 264;       // LDS row stride (bf16) of a hidden tile
 constexpr int kNG = 64;        // group maxima per signal
 constexpr int kRankPer = 8;    // survivors ranked per selection lane (rank path: <= 64 per signal)
-constexpr int kThetaLowBit = 15;   // lowest key bit the threshold search resolves
+constexpr int kThetaLowBit = 17;   // lowest key bit the threshold search resolves
 constexpr int kPFHidden = 8;       // A-operand k-steps in flight, hidden layers
 constexpr int kPFOut = 3;          // A-operand k-steps in flight, output layer
 
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             const int hbw = (int)wave_max_u32((uint32_t)(hb + 1)) - 1;
             // largest tau with >= n_cand maxima at or above it, resolved down to
             // bit kThetaLowBit (the low mantissa bits left at zero only lower
-            // tau by < 2^-8 relative: a still-safe bound, at most a few more
+            // tau by < 2^-6 relative: a still-safe bound, at most a few more
             // survivors, and fewer search steps)
             for (int bit = hbw; bit >= kThetaLowBit; --bit) {
                 const uint32_t t2 = tau | (1u << bit);
