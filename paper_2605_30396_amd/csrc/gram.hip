@@ -45,8 +45,9 @@ __global__ void dict_check_kernel(const float *__restrict__ D, int d, int K, int
 
 // DT: d x Kp feature-major; Dbf: Kp x 64 BF16 atom-major, Dlo and Dl2 the
 // BF16 roundings of what the previous parts leave (D = Dbf + Dlo + Dl2 to
-// ~2^-27 relative); D48: K x 48 FP32 atom-major; Dr: Kp x dpad FP32
-// atom-major; Dbfo: Dbf in MFMA operand order; all zero padded.
+// ~2^-27 relative); D48: K x 48 FP32 atom-major; Dr: Kp x dpad FP32 in
+// FP32 MFMA operand order; Dbfo: Dbf in BF16 MFMA operand order; all zero
+// padded.
 __global__ void dict_layout_kernel(const float *__restrict__ Dc, int d, int K, int Kp, float *__restrict__ DT,
                                    uint16_t *__restrict__ Dbf, uint16_t *__restrict__ Dlo, uint16_t *__restrict__ Dl2,
                                    float *__restrict__ D48, float *__restrict__ Dr, int dpad,
@@ -64,7 +65,7 @@ __global__ void dict_layout_kernel(const float *__restrict__ Dc, int d, int K, i
     Dl2[t] = f32_to_bf16(r1 - __uint_as_float((uint32_t)mid << 16));
     if (i < d) DT[(size_t)i * Kp + j] = v;
     if (j < K && i < 48) D48[(size_t)j * 48 + i] = v;
-    if (i < dpad) Dr[(size_t)j * dpad + i] = v;
+    if (i < dpad) Dr[op_order_f32(j, i, dpad)] = v;
 }
 
 // G[j][l] = <a_j, a_l>, summed in FP64 and rounded once; columns l >= K are 0.

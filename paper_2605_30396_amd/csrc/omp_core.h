@@ -201,8 +201,9 @@ __device__ __forceinline__ void alpha0_valu(const float *__restrict__ DT, int d,
 // so the values do not depend on the wave count).
 // The contraction runs over 16-feature chunks whose four k-steps take features
 // 4 kq + s (s = 0..3) in lane group kq, so the A operands of a whole chunk are
-// one 16-byte read per lane from the atom-major dictionary Dr (Kp x dpad,
-// zero padded): a wave's reads cover whole atom rows, and the next chunk is
+// one 16-byte read per lane.  Dr holds the dictionary in that operand order
+// (op_order_f32: per 16-atom block and chunk, 64 lanes x 4 floats, 1 KB
+// contiguous), so a wave's read is eight whole cache lines; the next chunk is
 // read while the current one is multiplied.  B operands come from the
 // feature-major signal tile in LDS.
 template <int E, int T, int NW>
@@ -232,7 +233,7 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, in
         for (int c = 0; c < CB; ++c) acc[b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
     const float *rowp[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) rowp[b] = Dr + (size_t)((ab0 + NW * b) * 16 + lr) * dpad + 4 * kq;
+    for (int b = 0; b < NB; ++b) rowp[b] = Dr + ((size_t)(ab0 + NW * b) * (dpad / 16) * 64 + lane) * 4;
     floatx4 an[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) an[b] = *reinterpret_cast<const floatx4 *>(rowp[b]);
@@ -242,7 +243,7 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, in
         for (int b = 0; b < NB; ++b) a[b] = an[b];
         if (f0 + 16 < dpad) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) an[b] = *reinterpret_cast<const floatx4 *>(rowp[b] + f0 + 16);
+            for (int b = 0; b < NB; ++b) an[b] = *reinterpret_cast<const floatx4 *>(rowp[b] + 16 * (f0 + 16));
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {

@@ -38,6 +38,14 @@ __host__ __device__ inline size_t op_order_index(int i, int f, int C) {
     return ((((size_t)(i >> 5) * (C >> 4) + (f >> 4)) * 64 + 32 * ((f >> 3) & 1) + (i & 31)) << 3) + (f & 7);
 }
 
+// Position of element (atom a, feature f) of a Kp x dpad FP32 dictionary in
+// the operand order of v_mfma_f32_16x16x4_f32 over 16-feature chunks: per
+// 16-atom block a / 16 and chunk f / 16, 64 lanes x 4 floats, lane
+// 16 ((f / 4) % 4) + a % 16 holding features 4 ((f / 4) % 4) .. + 3.
+__host__ __device__ inline size_t op_order_f32(int a, int f, int dpad) {
+    return ((((size_t)(a >> 4) * (dpad >> 4) + (f >> 4)) * 64 + 16 * ((f >> 2) & 3) + (a & 15)) << 2) + (f & 3);
+}
+
 struct DictDev {
     int d, K, Kp, E;
     const float *D;    // K x d atom-major FP32
@@ -48,7 +56,7 @@ struct DictDev {
     const uint16_t *Dl2;  // Kp x 64 BF16 low part bf16(D - Dbf - Dlo)
     const float *D48;     // K x 48 FP32 atom-major, features zero padded (d <= 48)
     const double *G64;    // K x K Gram, exact products summed in FP64 (not rounded)
-    const float *Dr;      // Kp x dpad FP32 atom-major, atoms and features zero padded (MFMA operands)
+    const float *Dr;      // Kp x dpad FP32 in MFMA operand order (op_order_f32), zero padded
     int dpad;             // d rounded up to 16
 };
 
@@ -195,7 +203,7 @@ struct sc_dict_s {
     uint16_t *Dbfo = nullptr;   // Dbf in MFMA operand order (the screening product)
     uint16_t *Dlo = nullptr;
     uint16_t *Dl2 = nullptr;
-    float *Dr = nullptr;    // Kp x dpad FP32 atom-major (MFMA operands)
+    float *Dr = nullptr;    // Kp x dpad FP32 in MFMA operand order (op_order_f32)
     float *D48 = nullptr;   // K x 48 FP32, atoms padded to 16-byte rows
     double *G64 = nullptr;  // K x K FP64 Gram (the FP64 refit's entries)
     int *status = nullptr;
