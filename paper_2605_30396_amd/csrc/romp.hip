@@ -21,6 +21,12 @@ namespace sc {
 constexpr int kRCpl = 4;           // candidates per lane (n_cand <= 32)
 constexpr int kRThreads = 256;
 constexpr int kMissQ = 256;        // fallback rows queued per wave before one atomic reserves their slots
+// Dictionary staged in LDS (LDSD): one 16-wave workgroup per compute unit
+// reads the candidate rows from its own copy of D48 (K x 48 FP32, 96 KB at
+// K = 512) instead of gathering them from L2, which bounded the correlation
+// stage; the miss queues are shorter to make room.
+constexpr int kRWavesL = 16;
+constexpr int kMissQL = 64;
 
 template <int KMAX>
 struct GroupScratch {
@@ -110,12 +116,22 @@ __device__ __forceinline__ float grp_resid2(const GroupScratch<KMAX> &gs, int n,
     return grp_sum(acc);
 }
 
-template <int KMAX>
-__global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict, const float *__restrict__ D48,
-                                                                    RompParams p) {
+template <int KMAX, bool LDSD>
+__global__ __launch_bounds__(LDSD ? 64 * kRWavesL : kRThreads) void omp_restricted_kernel(
+    DictDev dict, const float *__restrict__ D48g, RompParams p) {
+    constexpr int NWV = LDSD ? kRWavesL : kRThreads / 64;   // waves per workgroup
+    constexpr int MQ = LDSD ? kMissQL : kMissQ;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     RompWaveScratch<KMAX> *wsAll = reinterpret_cast<RompWaveScratch<KMAX> *>(smem_raw);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float *__restrict__ D48 = D48g;
+    if constexpr (LDSD) {   // the workgroup's copy of the dictionary rows, after the wave scratch
+        float *Ds = reinterpret_cast<float *>(smem_raw + sizeof(RompWaveScratch<KMAX>) * NWV);
+        for (int q = tid; q < dict.K * 12; q += 64 * NWV)
+            reinterpret_cast<float4 *>(Ds)[q] = reinterpret_cast<const float4 *>(D48g)[q];
+        __syncthreads();
+        D48 = Ds;
+    }
     const int g = lane & 7, grp = lane >> 3;
     RompWaveScratch<KMAX> &ws = wsAll[wave];
     GroupScratch<KMAX> &gs = ws.g[grp];
@@ -124,7 +140,7 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
     const float nanv = __builtin_nanf("");
     unsigned long long n_sig = 0, n_atoms = 0, n_miss = 0, n_refit = 0;
     // per-wave queue of fallback rows (wave-uniform fill level nq)
-    __shared__ int32_t miss_queue[kRThreads / 64][kMissQ];
+    __shared__ int32_t miss_queue[NWV][MQ];
     int32_t *mq = miss_queue[wave];
     int nq = 0;
     auto flush_misses = [&]() {
@@ -140,8 +156,8 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
     using vR = vecr<kRCpl>;
 
     const int64_t ngroups = (p.N + 7) / 8;
-    const int64_t gwave = (int64_t)blockIdx.x * (kRThreads / 64) + wave;
-    const int64_t wstride = (int64_t)gridDim.x * (kRThreads / 64);
+    const int64_t gwave = (int64_t)blockIdx.x * NWV + wave;
+    const int64_t wstride = (int64_t)gridDim.x * NWV;
     for (int64_t wg = gwave; wg < ngroups; wg += wstride) {
         const int64_t sig = wg * 8 + grp;
         const bool valid = sig < p.N;
@@ -414,7 +430,7 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
         const uint64_t mb = __ballot(miss && g == 0);
         if (mb) {
             const int cm = __popcll(mb);
-            if (nq + cm > kMissQ) flush_misses();
+            if (nq + cm > MQ) flush_misses();
             if (miss && g == 0) {
                 mq[nq + __popcll(mb & ((1ull << lane) - 1ull))] = (int32_t)sig;
                 n_miss += 1;
@@ -425,7 +441,7 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
     }
     flush_misses();
     if (p.stats) {   // one atomic per counter and workgroup
-        __shared__ unsigned int red[kRThreads / 64][4];
+        __shared__ unsigned int red[NWV][4];
         const unsigned long long v[4] = {n_sig, n_atoms, n_refit, n_miss};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -438,38 +454,53 @@ __global__ __launch_bounds__(kRThreads) void omp_restricted_kernel(DictDev dict,
         __syncthreads();
         if (tid < 4) {
             unsigned long long t = 0;
-            for (int w = 0; w < kRThreads / 64; ++w) t += red[w][tid];
+            for (int w = 0; w < NWV; ++w) t += red[w][tid];
             if (t) atomicAdd(p.stats + tid, t);
         }
     }
 }
 
-template <int KMAX>
-static hipError_t launch_romp_t(const DictDev &dict, const float *D48, const RompParams &p, hipStream_t st) {
-    const size_t smem = sizeof(RompWaveScratch<KMAX>) * (kRThreads / 64);
-    auto kern = omp_restricted_kernel<KMAX>;
-    static bool attr = false;
-    if (!attr) {
+template <int KMAX, bool LDSD>
+static hipError_t launch_romp_t(const DictDev &dict, const float *D48, const RompParams &p, size_t smem, int ncu,
+                                hipStream_t st) {
+    constexpr int NWV = LDSD ? kRWavesL : kRThreads / 64;
+    auto kern = omp_restricted_kernel<KMAX, LDSD>;
+    static size_t attr = 0;   // largest dynamic LDS size set so far
+    if (smem > attr) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
-        attr = true;
+        attr = smem;
     }
+    const int64_t nw = (p.N + 7) / 8;
+    const int64_t grid = LDSD ? std::max<int64_t>(1, std::min<int64_t>((nw + NWV - 1) / NWV, (int64_t)ncu))
+                              : std::max<int64_t>(1, std::min<int64_t>((nw + 3) / 4, (int64_t)ncu * 8));
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * NWV), smem, st, dict, D48, p);
+    return hipGetLastError();
+}
+
+template <int KMAX>
+static hipError_t launch_romp_k(const DictDev &dict, const float *D48, const RompParams &p, hipStream_t st) {
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t nw = (p.N + 7) / 8;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((nw + 3) / 4, (int64_t)ncu * 8));
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kRThreads), smem, st, dict, D48, p);
-    return hipGetLastError();
+    constexpr size_t lds_max = 160 * 1024;   // LDS of a gfx950 workgroup
+    // static LDS of the staged form: miss queues and the counter reduction
+    constexpr size_t kStaticL = sizeof(int32_t) * kRWavesL * kMissQL + sizeof(unsigned int) * kRWavesL * 4;
+    const size_t smemL = sizeof(RompWaveScratch<KMAX>) * kRWavesL + sizeof(float) * 48 * (size_t)dict.K;
+    if constexpr (KMAX <= 4) {
+        if (smemL + kStaticL <= lds_max)
+            return launch_romp_t<KMAX, true>(dict, D48, p, smemL, ncu, st);
+    }
+    return launch_romp_t<KMAX, false>(dict, D48, p, sizeof(RompWaveScratch<KMAX>) * (kRThreads / 64), ncu, st);
 }
 
 hipError_t launch_omp_restricted(const DictDev &dict, const float *D48, const RompParams &p, int kmax, hipStream_t st) {
     if (p.n_cand > 8 * kRCpl) return hipErrorInvalidValue;
     switch (kmax) {
-        case 4: return launch_romp_t<4>(dict, D48, p, st);
-        case 8: return launch_romp_t<8>(dict, D48, p, st);
-        case 12: return launch_romp_t<12>(dict, D48, p, st);
-        case 16: return launch_romp_t<16>(dict, D48, p, st);
+        case 4: return launch_romp_k<4>(dict, D48, p, st);
+        case 8: return launch_romp_k<8>(dict, D48, p, st);
+        case 12: return launch_romp_k<12>(dict, D48, p, st);
+        case 16: return launch_romp_k<16>(dict, D48, p, st);
         default: return hipErrorInvalidValue;
     }
 }
