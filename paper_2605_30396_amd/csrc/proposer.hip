@@ -100,7 +100,18 @@ __device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int 
     bf16x8 b[2][2];
 #pragma unroll
     for (int n = 0; n < 2; ++n) b[0][n] = ld_bf16x8(Hin + (32 * n + lr) * ldh + lk);
-    floatx16 acc[2] = {floatx16{}, floatx16{}};
+    // the accumulators start from the bias (both signal halves)
+    floatx16 acc[2];
+    {
+        floatx16 bacc;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const float4 bb = *reinterpret_cast<const float4 *>(bias + 32 * wave + 8 * g + 4 * (lane >> 5));
+            bacc[4 * g] = bb.x, bacc[4 * g + 1] = bb.y, bacc[4 * g + 2] = bb.z, bacc[4 * g + 3] = bb.w;
+        }
+        acc[0] = bacc;
+        acc[1] = bacc;
+    }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -119,10 +130,9 @@ __device__ __forceinline__ void dense_layer(const uint16_t *__restrict__ W, int 
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int i0 = 32 * wave + 8 * g + 4 * (lane >> 5);
-            const float4 bb = *reinterpret_cast<const float4 *>(bias + i0);
             uint2 pk;
-            pk.x = bf16_pack2(gelu_f(acc[n][4 * g + 0] + bb.x), gelu_f(acc[n][4 * g + 1] + bb.y));
-            pk.y = bf16_pack2(gelu_f(acc[n][4 * g + 2] + bb.z), gelu_f(acc[n][4 * g + 3] + bb.w));
+            pk.x = bf16_pack2(gelu_f(acc[n][4 * g + 0]), gelu_f(acc[n][4 * g + 1]));
+            pk.y = bf16_pack2(gelu_f(acc[n][4 * g + 2]), gelu_f(acc[n][4 * g + 3]));
             *reinterpret_cast<uint2 *>(Hout + j * kHS + i0) = pk;
         }
     }
@@ -227,9 +237,18 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         const int n0 = MT3 >= kPWaves ? 0 : wave / MT3;   // first signal half of the wave
         floatx16 acc[MPW][NPW];
 #pragma unroll
-        for (int q = 0; q < MPW; ++q)
+        for (int q = 0; q < MPW; ++q) {   // the MLP's accumulators start from the bias
+            floatx16 bacc = floatx16{};
+            if constexpr (!SCREEN) {
 #pragma unroll
-            for (int n = 0; n < NPW; ++n) acc[q][n] = floatx16{};
+                for (int g = 0; g < 4; ++g) {
+                    const float4 bb = *reinterpret_cast<const float4 *>(P.b3 + 32 * mblk(q) + 8 * g + 4 * (lane >> 5));
+                    bacc[4 * g] = bb.x, bacc[4 * g + 1] = bb.y, bacc[4 * g + 2] = bb.z, bacc[4 * g + 3] = bb.w;
+                }
+            }
+#pragma unroll
+            for (int n = 0; n < NPW; ++n) acc[q][n] = bacc;
+        }
         {
             constexpr int PF = kPFOut;
             bf16x8 a[PF][MPW];
@@ -262,7 +281,7 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         __syncthreads();   // every wave is done reading the layer-3 input before the scratch overlays it
         // writer index of this lane for its signals, and the signals
         const int wr = (MT3 >= kPWaves ? 2 * wave : 2 * (wave & (MT3 - 1))) + (lane >> 5);
-        // bias, optional logits, group maxima
+        // optional logits, group maxima
 #pragma unroll
         for (int n = 0; n < NPW; ++n) {
             const int j = 32 * (n0 + n) + lr;
@@ -274,12 +293,6 @@ __global__ __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                     if constexpr (SCREEN) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) acc[q][n][4 * g + r] = fabsf(acc[q][n][4 * g + r]);
-                    } else {
-                        const float4 bb = *reinterpret_cast<const float4 *>(P.b3 + i0);
-                        acc[q][n][4 * g + 0] += bb.x;
-                        acc[q][n][4 * g + 1] += bb.y;
-                        acc[q][n][4 * g + 2] += bb.z;
-                        acc[q][n][4 * g + 3] += bb.w;
                     }
                     if (logits && j < nt_sig) {
                         float4 o = {acc[q][n][4 * g], acc[q][n][4 * g + 1], acc[q][n][4 * g + 2],
