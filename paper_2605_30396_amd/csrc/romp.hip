@@ -126,6 +126,7 @@ __global__ __launch_bounds__(LDSD ? 64 * kRWavesL : kRThreads) void omp_restrict
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *__restrict__ D48 = D48g;
     if constexpr (LDSD) {   // the workgroup's copy of the dictionary rows, after the wave scratch
+        static_assert(sizeof(RompWaveScratch<KMAX>) % 16 == 0, "16-byte aligned dictionary copy");
         float *Ds = reinterpret_cast<float *>(smem_raw + sizeof(RompWaveScratch<KMAX>) * NWV);
         for (int q = tid; q < dict.K * 12; q += 64 * NWV)
             reinterpret_cast<float4 *>(Ds)[q] = reinterpret_cast<const float4 *>(D48g)[q];
