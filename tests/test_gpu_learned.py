@@ -303,6 +303,58 @@ def test_full_size_sampled_learned_encoder():
     h.destroy()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("K", [512, 1000])
+def test_restricted_dictionary_in_lds_and_from_l2(K):
+    """Restricted OMP with a step cap of 4 over caller-given candidate lists:
+    at K = 512 the dictionary rows fit in LDS and one 16-wave workgroup per
+    compute unit reads them there; at K = 1000 (192 KB of rows) they are read
+    from L2.  Either way the accepted codes equal the oracle's OMP restricted
+    to the same lists (selections on each signal's unique prefix, counts and
+    coefficients on well-separated signals), and a signal is sent to the
+    fallback exactly when the oracle's restricted residual exceeds eps."""
+    rng = I.rng_for(41)
+    D = I.random_dictionary(rng, K)
+    N, k, eps, cap = 4097, 8, 1e-2, 4
+    X, sup, _ = I.sparse_signals(rng, D, N, 3, 1e-3)
+    # 24 candidates by index: the generating support plus other atoms; every
+    # third list leaves out one support atom, so those signals mostly miss eps
+    cand = np.empty((N, 24), np.int32)
+    for i in range(N):
+        keep = sup[i][1:] if i % 3 == 0 else sup[i]
+        others = rng.choice(np.setdiff1d(np.arange(K), sup[i]), 24 - len(keep), replace=False)
+        cand[i] = np.sort(np.concatenate([keep, others]))
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    h.set_tuning(sc.TUNE_RESTRICTED_CAP, cap)
+    idx, coef, count, resid, miss_rows, miss_count = sc.omp_encode_restricted(
+        h, torch.from_numpy(X).to(DEV), k, eps, torch.from_numpy(cand).to(DEV))
+    torch.cuda.synchronize()
+    nm = int(miss_count.item())
+    miss = np.zeros(N, bool)
+    miss[miss_rows[:nm].cpu().numpy()] = True
+    g = {"idx": idx.cpu().numpy(), "coef": coef.cpu().numpy(), "count": count.cpu().numpy(),
+         "resid": resid.cpu().numpy()}
+    ref = oracle.omp(D, X, cap, eps, cand=cand, with_margin=True, with_path=True)
+    xn = np.linalg.norm(X.astype(np.float64), axis=1)
+    clear = np.abs(ref["resid"] - eps) > 1e-4 * xn   # away from the acceptance boundary
+    np.testing.assert_array_equal(miss[clear], ref["resid"][clear] > eps)
+    acc = ~miss
+    assert 0.2 * N < nm < 0.5 * N
+    sep = well_separated(D, X, ref, eps) & acc & clear
+    assert sep.sum() > 0.5 * acc.sum()
+    np.testing.assert_array_equal(g["count"][sep], ref["count"][sep])
+    np.testing.assert_array_equal(g["idx"][sep, :cap], ref["idx"][sep])
+    gc, rc = g["coef"][sep, :cap].astype(np.float64), ref["coef"][sep]
+    err = np.linalg.norm(gc - rc, axis=1) / np.maximum(np.linalg.norm(rc, axis=1), 1e-30)
+    assert err.max() <= 1e-4
+    r = np.linalg.norm(X[acc].astype(np.float64) - np.einsum(
+        "nk,nkd->nd", g["coef"][acc].astype(np.float64),
+        D.astype(np.float64)[np.maximum(g["idx"][acc], 0)] * (g["idx"][acc] >= 0)[:, :, None]), axis=1)
+    assert np.all(np.abs(r - g["resid"][acc]) <= 1e-5 * xn[acc] + 1e-7)
+    print("K", K, "misses", nm, "of", N, "separated", sep.mean())
+    h.destroy()
+
+
 def test_out_of_range_candidates_and_rows_are_ignored():
     """Caller-supplied lists are range-checked in the kernels: a candidate id
     outside [0, K) reads as -1 (a row whose first entry is out of range has no
