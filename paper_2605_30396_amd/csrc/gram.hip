@@ -43,9 +43,9 @@ __global__ void dict_check_kernel(const float *__restrict__ D, int d, int K, int
     }
 }
 
-// DT: d x Kp feature-major; Dbf: Kp x 64 BF16 atom-major, Dlo and Dl2 the
-// BF16 roundings of what the previous parts leave (D = Dbf + Dlo + Dl2 to
-// ~2^-27 relative); D48: K x 48 FP32 atom-major; Dr: Kp x dpad FP32 in
+// DT: d x Kp feature-major; Dbf: Kp x 64 BF16, Dlo and Dl2 the BF16
+// roundings of what the previous parts leave (D = Dbf + Dlo + Dl2 to ~2^-27
+// relative), all three in the operand order of the split-BF16 correlation; D48: K x 48 FP32 atom-major; Dr: Kp x dpad FP32 in
 // FP32 MFMA operand order; Dbfo: Dbf in BF16 MFMA operand order; all zero
 // padded.
 __global__ void dict_layout_kernel(const float *__restrict__ Dc, int d, int K, int Kp, float *__restrict__ DT,
@@ -59,10 +59,11 @@ __global__ void dict_layout_kernel(const float *__restrict__ Dc, int d, int K, i
     const uint16_t hi = f32_to_bf16(v);
     const float r1 = v - __uint_as_float((uint32_t)hi << 16);
     const uint16_t mid = f32_to_bf16(r1);
-    Dbf[t] = hi;
+    const size_t o = op_order_bf16x32(j, i);
+    Dbf[o] = hi;
     Dbfo[op_order_index(j, i, 64)] = hi;
-    Dlo[t] = mid;
-    Dl2[t] = f32_to_bf16(r1 - __uint_as_float((uint32_t)mid << 16));
+    Dlo[o] = mid;
+    Dl2[o] = f32_to_bf16(r1 - __uint_as_float((uint32_t)mid << 16));
     if (i < d) DT[(size_t)i * Kp + j] = v;
     if (j < K && i < 48) D48[(size_t)j * 48 + i] = v;
     if (i < dpad) Dr[op_order_f32(j, i, dpad)] = v;

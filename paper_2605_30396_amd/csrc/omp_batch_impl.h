@@ -7,14 +7,15 @@
 
 namespace sc {
 
-// Workgroup shape: the FP32 MFMA correlation of dictionaries of 128..512
-// atoms runs 8 waves on 32-signal tiles, so every dictionary read from the
-// cache feeds twice the signals (the correlation stage is bound by those
-// reads); the LDS tile (75 KB at K = 512) still lets two workgroups share a
-// compute unit.  Every other case runs 4 waves on 16-signal tiles.
+// Workgroup shape: the matrix-core correlations (FP32 or split BF16) of
+// dictionaries of 128..512 atoms run 8 waves on 32-signal tiles, so every
+// dictionary read from the cache feeds twice the signals (the correlation
+// stage is bound by those reads); the LDS tile (75 KB at K = 512) still lets
+// two workgroups share a compute unit.  Every other case runs 4 waves on
+// 16-signal tiles.
 template <int E, int MODE>
 struct BatchShape {
-    static constexpr int NW = (MODE == A0_MFMA_F32 && E >= 2 && E <= 8) ? 8 : kOmpWaves;
+    static constexpr int NW = ((MODE == A0_MFMA_F32 || MODE == A0_MFMA_BF16X6) && E >= 2 && E <= 8) ? 8 : kOmpWaves;
     static constexpr int T = 4 * NW;
 };
 

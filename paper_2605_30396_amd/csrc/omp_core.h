@@ -266,48 +266,75 @@ __device__ __forceinline__ void alpha0_mfma_f32(const float *__restrict__ Dr, in
                 acc[b][c];
 }
 
-// alpha0 tile (16 signals) from BF16 matrix cores at FP32 accuracy: D and x
-// are each split into three BF16 parts (v = vh + vm + vl, every part the
-// rounding of what the previous ones leave), and the six products whose
-// scale is at least 2^-16 are summed in FP32, smallest first:
+// alpha0 tile from BF16 matrix cores at FP32 accuracy: D and x are each
+// split into three BF16 parts (v = vh + vm + vl, every part the rounding of
+// what the previous ones leave), and the six products whose scale is at least
+// 2^-16 are summed in FP32, smallest first:
 //   Dm xm + Dl xh + Dh xl + Dm xh + Dh xm + Dh xh.
 // The products left out (Dm xl, Dl xm, Dl xl) and the parts' own rounding
 // are each <= 2^-27 |a_i x_i|, so they add <= 4 2^-27 ||x|| for a unit atom;
 // the FP32 accumulation error is that of an FP32 dot product.  Features are
-// padded to 64 (v_mfma_f32_16x16x32_bf16).
-template <int E>
+// padded to 64 (two k-steps of v_mfma_f32_16x16x32_bf16).  The waves split
+// the 16-atom blocks and 16-signal column blocks as the FP32 stage does
+// (MfmaF32Split); the dictionary parts are stored in the operand order of
+// this MFMA (op_order_bf16x32: per 16-atom block and 32-feature k-step, 64
+// lanes x 8 values, 1 KB contiguous), and the signal parts [3][T][kXhs] come
+// from LDS.
+template <int E, int T, int NW = kOmpWaves>
 __device__ __forceinline__ void alpha0_mfma_bf16x6(const uint16_t *__restrict__ Dh, const uint16_t *__restrict__ Dm,
                                                    const uint16_t *__restrict__ Dl, const uint16_t *__restrict__ Xh,
                                                    float *__restrict__ A0, int wave, int lane) {
-    constexpr int Kp = 64 * E, MT = Kp / 16, NB = MT / kOmpWaves;
-    const uint16_t *Xm = Xh + 16 * kXhs, *Xl = Xm + 16 * kXhs;
+    using S = MfmaF32Split<E, T, NW>;
+    constexpr int Kp = 64 * E, MT = S::MT, NB = S::NB, CB = S::CBW;
+    static_assert(S::ok, "MFMA tile shape");
+    const uint16_t *Xm = Xh + T * kXhs, *Xl = Xm + T * kXhs;
     const int lr = lane & 15, kq = lane >> 4;
-    floatx4 acc[NB];
+    const int ab0 = MT >= NW ? wave : wave % MT;            // first atom block of this wave
+    const int cb0 = MT >= NW ? 0 : (wave / MT) * CB;        // first column block of this wave
+    const bool busy = cb0 < S::CB;   // waves past the last column block stay idle
+    floatx4 acc[NB][CB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int k0 = 0; k0 < 64; k0 += 32) {
-        const bf16x8 bh = ld_bf16x8(Xh + lr * kXhs + k0 + 8 * kq);
-        const bf16x8 bm = ld_bf16x8(Xm + lr * kXhs + k0 + 8 * kq);
-        const bf16x8 bl = ld_bf16x8(Xl + lr * kXhs + k0 + 8 * kq);
+        for (int c = 0; c < CB; ++c) acc[b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (busy) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const size_t off = (size_t)((wave + kOmpWaves * b) * 16 + lr) * 64 + k0 + 8 * kq;
-            const bf16x8 ah = ld_bf16x8(Dh + off);
-            const bf16x8 am = ld_bf16x8(Dm + off);
-            const bf16x8 al = ld_bf16x8(Dl + off);
-            acc[b] = mfma16(am, bm, acc[b]);
-            acc[b] = mfma16(al, bh, acc[b]);
-            acc[b] = mfma16(ah, bl, acc[b]);
-            acc[b] = mfma16(am, bh, acc[b]);
-            acc[b] = mfma16(ah, bm, acc[b]);
-            acc[b] = mfma16(ah, bh, acc[b]);
+        for (int ks = 0; ks < 2; ++ks) {
+            bf16x8 bh[CB], bm[CB], bl[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int row = ((cb0 + c) * 16 + lr) * kXhs + 32 * ks + 8 * kq;
+                bh[c] = ld_bf16x8(Xh + row);
+                bm[c] = ld_bf16x8(Xm + row);
+                bl[c] = ld_bf16x8(Xl + row);
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const size_t off = (((size_t)(ab0 + NW * b) * 2 + ks) * 64 + lane) * 8;
+                const bf16x8 ah = ld_bf16x8(Dh + off);
+                const bf16x8 am = ld_bf16x8(Dm + off);
+                const bf16x8 al = ld_bf16x8(Dl + off);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    acc[b][c] = mfma16(am, bm[c], acc[b][c]);
+                    acc[b][c] = mfma16(al, bh[c], acc[b][c]);
+                    acc[b][c] = mfma16(ah, bl[c], acc[b][c]);
+                    acc[b][c] = mfma16(am, bh[c], acc[b][c]);
+                    acc[b][c] = mfma16(ah, bm[c], acc[b][c]);
+                    acc[b][c] = mfma16(ah, bh[c], acc[b][c]);
+                }
+            }
         }
     }
     __syncthreads();   // every wave has read the signal parts, which may share the alpha0 tile
+    if (busy) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-        *reinterpret_cast<floatx4 *>(A0 + lr * a0_stride(Kp) + (wave + kOmpWaves * b) * 16 + 4 * kq) = acc[b];
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                *reinterpret_cast<floatx4 *>(A0 + ((cb0 + c) * 16 + lr) * a0_stride(Kp) + (ab0 + NW * b) * 16 +
+                                             4 * kq) = acc[b][c];
+    }
 }
 
 // The E Gram-row entries of this lane (16-byte aligned for E % 4 == 0).
@@ -659,7 +686,7 @@ struct CodeStage {
 };
 
 // One tile of T signals: load, alpha0 by `mode` (A0_VALU or A0_MFMA_F32; or
-// A0_MFMA_BF16X6 when kSplitOK, T == 16 and the LDS holds the split parts),
+// A0_MFMA_BF16X6 when kSplitOK and the LDS holds the split parts),
 // then each wave encodes its signals (into `stage` when given).
 template <int E, int KMAX, int T, bool kSplitOK, int RCQ, int NW = kOmpWaves>
 __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p, int mode, int64_t s0, int nt,
@@ -680,12 +707,12 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
             done = true;
         }
     }
-    if constexpr (kSplitOK && T == 16 && NW == kOmpWaves) {   // BF16 parts of one 16-signal column block
+    if constexpr (kSplitOK && MfmaF32Split<E, T, NW>::ok) {
         if (mode == A0_MFMA_BF16X6) {
             // signal parts [3][T][kXhs]: x = xh + xm + xl in BF16
             uint16_t *Xh = split_in_a0(T, Kp) ? reinterpret_cast<uint16_t *>(A0)
                                               : reinterpret_cast<uint16_t *>(Xt + 64 * xt_stride(T));
-            for (int q = tid; q < T * 64; q += kOmpThreads) {
+            for (int q = tid; q < T * 64; q += 64 * NW) {
                 const int s = q >> 6, f = q & 63;
                 const float v = Xt[f * xt_stride(T) + s];
                 const uint16_t hi = bf16_bits(v);
@@ -696,7 +723,7 @@ __device__ __forceinline__ void omp_tile(const DictDev &dict, const OmpParams &p
                 Xh[(2 * T + s) * kXhs + f] = bf16_bits(r1 - bf16_to_f32(mid));
             }
             __syncthreads();
-            alpha0_mfma_bf16x6<E>(dict.Dbf, dict.Dlo, dict.Dl2, Xh, A0, wave, lane);
+            alpha0_mfma_bf16x6<E, T, NW>(dict.Dbf, dict.Dlo, dict.Dl2, Xh, A0, wave, lane);
             done = true;
         }
     }

@@ -46,14 +46,23 @@ __host__ __device__ inline size_t op_order_f32(int a, int f, int dpad) {
     return ((((size_t)(a >> 4) * (dpad >> 4) + (f >> 4)) * 64 + 16 * ((f >> 2) & 3) + (a & 15)) << 2) + (f & 3);
 }
 
+// Position of element (atom a, feature f < 64) of a Kp x 64 BF16 dictionary
+// part in the operand order of v_mfma_f32_16x16x32_bf16: per 16-atom block
+// a / 16 and 32-feature k-step f / 32, 64 lanes x 8 values, lane
+// 16 ((f / 8) % 4) + a % 16 holding features 8 ((f / 8) % 4) .. + 7.
+__host__ __device__ inline size_t op_order_bf16x32(int a, int f) {
+    return ((((size_t)(a >> 4) * 2 + (f >> 5)) * 64 + 16 * ((f >> 3) & 3) + (a & 15)) << 3) + (f & 7);
+}
+
 struct DictDev {
     int d, K, Kp, E;
     const float *D;    // K x d atom-major FP32
     const float *DT;   // dt_rows(d) x Kp feature-major FP32, zero padded atoms and rows >= d
     const float *G;    // K x Kp FP32 Gram rows, zero padded columns
-    const uint16_t *Dbf;  // Kp x 64 BF16 atom-major, features and atoms zero padded
-    const uint16_t *Dlo;  // Kp x 64 BF16 middle part bf16(D - Dbf) (split-BF16 products)
-    const uint16_t *Dl2;  // Kp x 64 BF16 low part bf16(D - Dbf - Dlo)
+    // split-BF16 parts of D, Kp x 64 each in op_order_bf16x32, zero padded:
+    const uint16_t *Dbf;  // bf16(D)
+    const uint16_t *Dlo;  // bf16(D - Dbf)
+    const uint16_t *Dl2;  // bf16(D - Dbf - Dlo)
     const float *D48;     // K x 48 FP32 atom-major, features zero padded (d <= 48)
     const double *G64;    // K x K Gram, exact products summed in FP64 (not rounded)
     const float *Dr;      // Kp x dpad FP32 in MFMA operand order (op_order_f32), zero padded
