@@ -6,17 +6,20 @@ K = 512 Gaussian unit-norm dictionary (coefficients U[-1,1]) plus N(0, sigma=1e-
 noise; k = 12, eps = 1e-2.  The support proposer is trained first (untimed)
 on 2,000,000 signals of the same generator labelled by the FP32 encoder.
 
-One step = the whole hot path over the batch: the learned encoder (BF16 MFMA
-proposer -> top-24 candidates -> restricted Batch-OMP -> full-OMP fallback on
-the signals whose residual exceeds eps), then the radiance of every code at
-one view direction per Gaussian.  Inputs are resident in HBM before timing.
-The comparators (plain FP32 Batch-OMP, BF16 precision form, untrained
-proposer) are timed on the same inputs and reported beside it, and so is the
-16-scene batch (sizes log-uniform in 50k..6M, K in {128, 256, 512}, k in
-{4, 8, 12, 16}, eps = 0) encoded in one autotuned persistent launch.
+One step = the whole hot path over the batch: the learned+BF16 encoder (BF16
+MFMA proposer -> top-24 candidates -> restricted Batch-OMP -> full-OMP
+fallback, whose correlations D^T x run on BF16 matrix cores as six split-BF16
+products of FP32 accuracy, on the signals whose residual exceeds eps), then
+the radiance of every code at one view direction per Gaussian.  Inputs are
+resident in HBM before timing.  The comparators (plain FP32 Batch-OMP, the
+BF16 precision form alone, the learned encoder with an FP32-correlation
+fallback, an untrained proposer, correlation screening) are timed on the
+same inputs and reported beside it, and so is the 16-scene batch (sizes
+log-uniform in 50k..6M, K in {128, 256, 512}, k in {4, 8, 12, 16}, eps = 0)
+encoded in one autotuned persistent launch and as one launch per scene.
 
-Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: this
-build runs on one GPU.
+Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: the
+encoder is measured on one GPU.
 """
 from __future__ import annotations
 
@@ -330,7 +333,7 @@ def main():
         tuned_learned = saved["learned"]
         h.set_tuning(sc.TUNE_RESTRICTED_CAP, tuned_learned["restricted_cap"])
     else:
-        tuned_learned = autotune.tune_learned(h, prop, Xg, k, eps, use_cache=False)
+        tuned_learned = autotune.tune_learned(h, prop, Xg, k, eps, sc.PREC_BF16, use_cache=False)
         if args.tuning:
             with open(args.tuning, "w") as f:
                 json.dump({"encoder": tuned, "learned": tuned_learned}, f)
@@ -408,16 +411,15 @@ def main():
 
     results = {}
 
-    # ---- headline: learned encoder (BF16 proposer) + radiance, one step ----
+    # ---- headline: learned+BF16 encoder + radiance, one step ----
     def headline(marks):
-        learned_step(prop, 0, marks)
+        learned_step(prop, sc.PREC_BF16, marks)
         sc.sh_eval_sparse(h, idx, coef, count, dirg, sc.DIRS_PER_SIGNAL, out=rgb)
         marks[4].record(stream)
 
     head_ms_step, ph, st = time_variant(headline, 5)
-    results["learned_bf16_proposer"] = dict(ms=sum(ph[:3]), phases_ms=dict(proposer=ph[0], restricted=ph[1],
-                                                                          fallback=ph[2]),
-                                            fallback_frac=st["fallbacks"] / (N * args.steps), **quality())
+    results["learned_bf16"] = dict(ms=sum(ph[:3]), phases_ms=dict(proposer=ph[0], restricted=ph[1], fallback=ph[2]),
+                                   fallback_frac=st["fallbacks"] / (N * args.steps), **quality())
     eval_ms = ph[3]
     # the same codes' radiance from CSC columns (packed untimed): reads only the non-zeros
     colptr_h, rows_h, vals_h = sc.pack_csc(idx, coef, count)
@@ -458,15 +460,17 @@ def main():
         _, ph2, st2 = time_variant(run, 2)
         results[name] = dict(ms=ph2[0], **quality())
         log(f"{name} {ph2[0]:.2f} ms")
-    _, ph2, st2 = time_variant(lambda m: learned_step(prop, sc.PREC_BF16, m), 4)
-    results["learned_bf16_fallback"] = dict(ms=sum(ph2), phases_ms=dict(proposer=ph2[0], restricted=ph2[1],
-                                                                       fallback=ph2[2]),
-                                            fallback_frac=st2["fallbacks"] / (N * args.steps), **quality())
-    _, ph2, st2 = time_variant(lambda m: learned_step(untrained, 0, m), 4)
+    _, ph2, st2 = time_variant(lambda m: learned_step(prop, 0, m), 4)
+    results["learned_bf16_proposer_fp32_fallback"] = dict(ms=sum(ph2), phases_ms=dict(proposer=ph2[0],
+                                                                                     restricted=ph2[1],
+                                                                                     fallback=ph2[2]),
+                                                          fallback_frac=st2["fallbacks"] / (N * args.steps),
+                                                          **quality())
+    _, ph2, st2 = time_variant(lambda m: learned_step(untrained, sc.PREC_BF16, m), 4)
     results["learned_untrained"] = dict(ms=sum(ph2), phases_ms=dict(proposer=ph2[0], restricted=ph2[1],
                                                                    fallback=ph2[2]),
                                         fallback_frac=st2["fallbacks"] / (N * args.steps), **quality())
-    _, ph2, st2 = time_variant(lambda m: learned_step(None, 0, m), 4)
+    _, ph2, st2 = time_variant(lambda m: learned_step(None, sc.PREC_BF16, m), 4)
     results["screened_top24"] = dict(ms=sum(ph2), phases_ms=dict(screen=ph2[0], restricted=ph2[1],
                                                                 fallback=ph2[2]),
                                      fallback_frac=st2["fallbacks"] / (N * args.steps), **quality())
@@ -609,7 +613,7 @@ def main():
         del X2, pos2, dc2
 
     # ---- per-kernel rates of the headline step, roofline of the dominant one ----
-    phs = results["learned_bf16_proposer"]["phases_ms"]
+    phs = results["learned_bf16"]["phases_ms"]
     ok = np.ones(N, bool)
     ok[miss_np] = False
     n_ok = cnt_head[ok].astype(np.float64)
@@ -622,8 +626,8 @@ def main():
                            (phs["restricted"] * 1e-3) / 1e12, src=("romp.hip", "wave.h", "sc_internal.h")),
         "fallback": dict(kernel="omp_batch_kernel", bound="alu", unit="TFLOP/s", peak=FP32_VALU_PEAK_TFLOPS,
                          achieved=batch_omp_flops(K, d, cnt_head[miss_np]) / (phs["fallback"] * 1e-3) / 1e12,
-                         src=("omp_core.h", "omp_batch_impl.h", "omp_batch_mfma.hip", "omp_batch_valu.hip", "mfma.h", "wave.h",
-                              "sc_internal.h")),
+                         src=("omp_core.h", "omp_batch_impl.h", "omp_batch_bf16.hip", "omp_batch_mfma.hip",
+                              "omp_batch_valu.hip", "mfma.h", "wave.h", "sc_internal.h")),
         "radiance": dict(kernel="sh_eval_kernel", bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
                          achieved=sh_eval_bytes(N, k) / (eval_ms * 1e-3) / 1e9, src=("sh_eval.hip", "sh_basis.h", "sc_internal.h")),
         "radiance_nonzero_bytes": dict(kernel="sh_eval_kernel", bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
@@ -662,7 +666,7 @@ def main():
                                "encode + one-view radiance",
                    "N": N, "K": K, "k": k, "eps": eps, "n_cand": N_CAND, "encoder_tuning": tuned,
                    "learned_tuning": tuned_learned},
-        "speedup_vs_plain_fp32": (round(plain["ms"] / results["learned_bf16_proposer"]["ms"], 4) if plain else None),
+        "speedup_vs_plain_fp32": (round(plain["ms"] / results["learned_bf16"]["ms"], 4) if plain else None),
         "comparators": {k2: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k2, v in results.items()},
         "workloads": workloads,
