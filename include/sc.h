@@ -128,7 +128,8 @@ int sc_dict_gram(sc_dict h, float *G_out, void *stream);
  * FP32 (Dm xm + Dl xh + Dh xl + Dm xh + Dh xm + Dh xh).  The products left
  * out and the parts' own rounding add <= 4 * 2^-27 ||x|| per unit atom, so
  * the correlations have the accuracy of FP32 dot products, at half the
- * matrix-core time of FP32 operands.  The Gram-form update, the factor,
+ * matrix-core time of FP32 operands (32-signal tiles on eight waves when
+ * 64 < K <= 512, else 16-signal tiles).  The Gram-form update, the factor,
  * the stop test and the coefficients are FP32 as in the default path.
  * Supports whose Cholesky condition estimate (max l_ii / min l_ii)^2 exceeds
  * 1e3 are refit in FP64 unless SC_NO_FP64_REFIT.
