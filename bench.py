@@ -662,8 +662,9 @@ def main():
         "dtype": "bf16+f32",
         "data": "synthetic",
         "config": {"workload": "learned-form: N=6e6 signals d=45, K=512 Gaussian unit-norm dictionary, 4-sparse "
-                               "U[-1,1] + N(0,sigma=1e-3) noise, k=12, eps=1e-2, top-24 candidates; step = learned "
-                               "encode + one-view radiance",
+                               "U[-1,1] + N(0,sigma=1e-3) noise, k=12, eps=1e-2, top-24 candidates; step = learned+BF16 "
+                               "encode (BF16 proposer, split-BF16 correlations in the full-OMP fallback) + one-view "
+                               "radiance",
                    "N": N, "K": K, "k": k, "eps": eps, "n_cand": N_CAND, "encoder_tuning": tuned,
                    "learned_tuning": tuned_learned},
         "speedup_vs_plain_fp32": (round(plain["ms"] / results["learned_bf16"]["ms"], 4) if plain else None),
