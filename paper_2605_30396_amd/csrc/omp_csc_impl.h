@@ -2,15 +2,15 @@
 // variable-length codes column by column; Sec. 3.2 varies their length by the
 // tolerance): one pass over the signals, no padded N x k codes in memory.
 //
-// Workgroups take 16-signal tiles in increasing order from a ticket counter,
-// so every tile below the one a workgroup holds has been taken by a running
-// workgroup.  A tile's codes are encoded into an LDS stage (the same tile
-// body as the padded encoder) and its number of non-zeros is published in a
-// per-tile descriptor; its column offset is found by looking back over the
-// descriptors of the tiles before it (decoupled look-back: a descriptor
+// Workgroups take 16- or 32-signal tiles in increasing order from a ticket
+// counter, so every tile below the one a workgroup holds has been taken by a
+// running workgroup.  A tile's codes are encoded into an LDS stage (the same
+// tile body as the padded encoder) and its number of non-zeros is published
+// in a per-tile descriptor; its column offset is found by looking back over
+// the descriptors of the tiles before it (decoupled look-back: a descriptor
 // holds either the tile's own count, or the inclusive count of every tile up
 // to it).  The columns are then written at their offsets, in signal order.
-// Only the descriptors (8 bytes per 16 signals) live in the workspace.
+// Only the descriptors (8 bytes per tile) live in the workspace.
 //
 // A code whose support is ill-conditioned is written with its FP32
 // coefficients and its column pointer stored as -(offset + 1); the refit pass
@@ -76,24 +76,39 @@ __device__ __forceinline__ int64_t look_back(uint64_t *desc, int64_t t, int64_t 
     return excl;
 }
 
+// Tile shape: with a matrix-core correlation stage and 128..512 atoms, 8
+// waves on 32-signal tiles (as the padded encoder) when the tile and its two
+// code stages still let two workgroups share a compute unit, and then held to
+// 128 VGPRs so that both fit; otherwise 4 waves on 16-signal tiles.
+template <int E, int KMAX, int MODE>
+struct CscShape {
+    static constexpr bool wide =
+        (MODE == A0_MFMA_F32 || MODE == A0_MFMA_BF16X6) && E >= 2 && E <= 8 &&
+        omp_tile_lds(32, 64 * E, MODE == A0_MFMA_BF16X6) + 2 * sizeof(int32_t) * (2 * 32 * KMAX + 32) <= 80 * 1024;
+    static constexpr int NW = wide ? 8 : kOmpWaves;
+    static constexpr int T = wide ? 32 : kCscTile;
+};
+
 // Per workgroup a two-deep pipeline: tile i is encoded into one LDS stage
 // and its count published; then tile i-1 (in the other stage) gets its
 // offset and is written out.  By then the tiles before i-1 have had a whole
 // tile's time to publish their counts, so the look-back seldom waits, and a
 // slow tile does not stall the workgroups behind it.
 template <int E, int KMAX, int MODE, int RCQ>
-__global__ __launch_bounds__(kOmpThreads) void omp_csc_kernel(DictDev dict, OmpParams p, int64_t *__restrict__ colptr,
-                                                              int32_t *__restrict__ rows, float *__restrict__ vals,
-                                                              int64_t cap, CscHeader *hdr, uint64_t *desc) {
+__global__ __launch_bounds__((64 * CscShape<E, KMAX, MODE>::NW))
+__attribute__((amdgpu_waves_per_eu(CscShape<E, KMAX, MODE>::wide ? 4 : 1))) void omp_csc_kernel(
+    DictDev dict, OmpParams p, int64_t *__restrict__ colptr, int32_t *__restrict__ rows, float *__restrict__ vals,
+    int64_t cap, CscHeader *hdr, uint64_t *desc) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int Kp = 64 * E;
-    constexpr int kStageWords = 2 * kCscTile * KMAX + kCscTile;   // idx, coef, count of one stage
-    const size_t tile_lds = omp_tile_lds(kCscTile, Kp, MODE == A0_MFMA_BF16X6);
+    constexpr int T = CscShape<E, KMAX, MODE>::T, NW = CscShape<E, KMAX, MODE>::NW;
+    constexpr int kStageWords = 2 * T * KMAX + T;   // idx, coef, count of one stage
+    const size_t tile_lds = omp_tile_lds(T, Kp, MODE == A0_MFMA_BF16X6);
     int32_t *stage_base = reinterpret_cast<int32_t *>(smem_raw + tile_lds);
-    __shared__ int64_t col_off[kCscTile];
+    __shared__ int64_t col_off[T];
     __shared__ int64_t tile_sh;
     OmpTally tally;
-    const int64_t N = p.N, ntiles = (N + kCscTile - 1) / kCscTile;
+    const int64_t N = p.N, ntiles = (N + T - 1) / T;
     const int k = p.k;
     int64_t prev = -1;   // the staged tile waiting for its offset (wave-uniform)
     int buf = 0;
@@ -107,43 +122,42 @@ __global__ __launch_bounds__(kOmpThreads) void omp_csc_kernel(DictDev dict, OmpP
         const int lane = tid & 63, wave = tid >> 6;
         if (t < ntiles) {   // encode tile t into stage `buf`, publish its count
             int32_t *sb = stage_base + buf * kStageWords;
-            const CodeStage stage{sb, reinterpret_cast<float *>(sb + kCscTile * KMAX), sb + 2 * kCscTile * KMAX};
-            const int64_t s0 = t * kCscTile;
-            const int nt = (int)min<int64_t>(kCscTile, N - s0);
-            omp_tile<E, KMAX, kCscTile, MODE == A0_MFMA_BF16X6, RCQ>(dict, p, MODE, s0, nt, smem_raw, tid, tally,
-                                                                     &stage);
+            const CodeStage stage{sb, reinterpret_cast<float *>(sb + T * KMAX), sb + 2 * T * KMAX};
+            const int64_t s0 = t * T;
+            const int nt = (int)min<int64_t>(T, N - s0);
+            omp_tile<E, KMAX, T, MODE == A0_MFMA_BF16X6, RCQ, NW>(dict, p, MODE, s0, nt, smem_raw, tid, tally, &stage);
             __syncthreads();
             if (wave == 0) {
                 int64_t c = lane < nt ? code_nnz(stage.cnt[lane]) : 0;
 #pragma unroll
-                for (int off = 1; off < kCscTile; off <<= 1) c += __shfl_xor(c, off, 64);
+                for (int off = 1; off < T; off <<= 1) c += __shfl_xor(c, off, 64);
                 if (lane == 0) publish_count(desc, t, c);
             }
         }
         if (prev >= 0) {   // offset of tile prev, then its columns
             const int32_t *sb = stage_base + (buf ^ 1) * kStageWords;
             const int32_t *st_idx = sb;
-            const float *st_coef = reinterpret_cast<const float *>(sb + kCscTile * KMAX);
-            const int32_t *st_cnt = sb + 2 * kCscTile * KMAX;
-            const int64_t s0 = prev * kCscTile;
-            const int nt = (int)min<int64_t>(kCscTile, N - s0);
+            const float *st_coef = reinterpret_cast<const float *>(sb + T * KMAX);
+            const int32_t *st_cnt = sb + 2 * T * KMAX;
+            const int64_t s0 = prev * T;
+            const int nt = (int)min<int64_t>(T, N - s0);
             if (wave == 0) {
                 const int64_t c = lane < nt ? code_nnz(st_cnt[lane]) : 0;
                 int64_t incl = c;
 #pragma unroll
-                for (int off = 1; off < kCscTile; off <<= 1) {
+                for (int off = 1; off < T; off <<= 1) {
                     const int64_t u = __shfl_up(incl, off, 64);
                     if (lane >= off) incl += u;
                 }
-                const int64_t agg = __shfl(incl, kCscTile - 1, 64);
+                const int64_t agg = __shfl(incl, T - 1, 64);
                 int64_t excl = 0;
                 if (lane == 0) excl = look_back(desc, prev, agg, &hdr->error);
                 excl = __shfl(excl, 0, 64);
-                if (lane < kCscTile) col_off[lane] = excl + incl - c;
+                if (lane < T) col_off[lane] = excl + incl - c;
                 if (lane == 0 && prev == ntiles - 1) colptr[N] = excl + agg;
             }
             __syncthreads();
-            for (int s = wave; s < nt; s += kOmpWaves) {
+            for (int s = wave; s < nt; s += NW) {
                 const int cnt = st_cnt[s];
                 const int n = code_nnz(cnt);
                 const int64_t o = col_off[s];
@@ -159,7 +173,7 @@ __global__ __launch_bounds__(kOmpThreads) void omp_csc_kernel(DictDev dict, OmpP
         buf ^= 1;
     }
     if (p.stats) {   // one pair of atomics per workgroup
-        __shared__ unsigned long long red[kOmpWaves][2];
+        __shared__ unsigned long long red[NW][2];
         if ((threadIdx.x & 63) == 0) {
             red[threadIdx.x >> 6][0] = tally.sig;
             red[threadIdx.x >> 6][1] = tally.atoms;
@@ -167,7 +181,7 @@ __global__ __launch_bounds__(kOmpThreads) void omp_csc_kernel(DictDev dict, OmpP
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long sg = 0, at = 0;
-            for (int w = 0; w < kOmpWaves; ++w) {
+            for (int w = 0; w < NW; ++w) {
                 sg += red[w][0];
                 at += red[w][1];
             }
@@ -183,8 +197,9 @@ template <int E, int KMAX, int MODE, int RCQ>
 static hipError_t launch_csc_t(const DictDev &dict, const OmpParams &p, int64_t *colptr, int32_t *rows, float *vals,
                                int64_t cap, void *ws, hipStream_t st) {
     constexpr int Kp = 64 * E;
-    const size_t smem = omp_tile_lds(kCscTile, Kp, MODE == A0_MFMA_BF16X6) +
-                        2 * sizeof(int32_t) * (2 * kCscTile * KMAX + kCscTile);   // two code stages
+    constexpr int T = CscShape<E, KMAX, MODE>::T, NW = CscShape<E, KMAX, MODE>::NW;
+    const size_t smem = omp_tile_lds(T, Kp, MODE == A0_MFMA_BF16X6) +
+                        2 * sizeof(int32_t) * (2 * T * KMAX + T);   // two code stages
     auto kern = omp_csc_kernel<E, KMAX, MODE, RCQ>;
     static bool attr_set = false;
     if (!attr_set) {
@@ -193,17 +208,17 @@ static hipError_t launch_csc_t(const DictDev &dict, const OmpParams &p, int64_t 
         attr_set = true;
     }
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kOmpThreads, smem) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 64 * NW, smem) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t ntiles = (p.N + kCscTile - 1) / kCscTile;
+    const int64_t ntiles = (p.N + T - 1) / T;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)ncu * per_cu));
     CscHeader *hdr = reinterpret_cast<CscHeader *>(ws);
     uint64_t *desc = reinterpret_cast<uint64_t *>(reinterpret_cast<unsigned char *>(ws) + 256);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kOmpThreads), smem, st, dict, p, colptr, rows, vals, cap, hdr,
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64 * NW), smem, st, dict, p, colptr, rows, vals, cap, hdr,
                        desc);
     return hipGetLastError();
 }
