@@ -154,8 +154,8 @@ int sc_omp_encode(sc_dict h, const float *X, int64_t N, int k, float eps, int fl
  *   SC_TUNE_ROW_CACHE  Gram rows of the first selected atoms kept in
  *     registers by the encoder: 0 (default for K > 256: every row re-read
  *     from cache memory when the correlations are formed) or 4 (applies to
- *     K <= 512 here; the batched encoder applies its own row_cache setting to
- *     dictionaries of K <= 256 only).
+ *     K <= 512 here; the batched encoder has its own row_cache setting, see
+ *     sc_batch_tuning).
  *   SC_TUNE_ROW_CACHE_BF16  the same choice for the split-BF16 form
  *     (SC_PREC_BF16), whose encoder holds more registers, so its best value
  *     can differ.
@@ -519,8 +519,9 @@ typedef struct {
  * depend on it beyond FP32 rounding order).
  *   tile       signals per workgroup tile: 16 or 32 (0 = 16)
  *   row_cache  Gram rows kept in registers: 0 or 4 (4 applies to the
- *              scenes with K <= 256; larger dictionaries re-read every row,
- *              which keeps the merged kernel within 128 registers)
+ *              scenes with K <= 256; scenes of K > 256 keep 2 when k <= 12
+ *              and re-read every row when k > 12, which keeps the merged
+ *              kernel within 128 registers)
  *   wg_per_cu  persistent workgroups per compute unit, 0 = as many as fit
  *   order      SC_ORDER_COST: scenes taken most expensive tile first;
  *              SC_ORDER_GIVEN: in the order of the array

@@ -72,6 +72,14 @@ __device__ __forceinline__ OmpParams scene_params(const SceneDesc &s) {
 template <int T, int MODE>
 constexpr int multi_waves() { return (T == 32 || MODE == A0_MFMA_F32) ? 8 : kOmpWaves; }
 
+// Gram rows a class body keeps in registers when the launch asks for the row
+// cache.  The merged kernel holds a few more live values across its tile
+// loop than the single-dictionary kernel, and the largest bodies are at the
+// 128-register limit there already: the 512-atom bodies keep two rows up to
+// a cap of 12 (four spill) and none at 16.
+template <int E, int KMAX, int RCQ>
+constexpr int multi_rows() { return RCQ == 0 ? 0 : E <= 4 ? RCQ : KMAX <= 12 ? 2 : 0; }
+
 template <int T, int RCQ, int MODE>
 __global__ __launch_bounds__((64 * multi_waves<T, MODE>())) __attribute__((amdgpu_waves_per_eu(4)))
 void omp_multi_kernel(MultiArgs a) {
@@ -109,7 +117,7 @@ void omp_multi_kernel(MultiArgs a) {
         const int nt = (int)min<int64_t>(T, sd.N - s0);
 #define SC_BODY(EI, EE, KK)                                                                            \
     case 4 * EI + KK / 4 - 1:                                                                          \
-        omp_tile<EE, KK, T, false, (EE <= 4 ? RCQ : 0), NW>(dict, p, MODE, s0, nt, smem_raw, tidv, tally); \
+        omp_tile<EE, KK, T, false, multi_rows<EE, KK, RCQ>(), NW>(dict, p, MODE, s0, nt, smem_raw, tidv, tally); \
         break;
         switch (sd.cls) {
             SC_BODY(0, 1, 4) SC_BODY(0, 1, 8) SC_BODY(0, 1, 12) SC_BODY(0, 1, 16)
