@@ -33,7 +33,7 @@ struct SceneDesc {
     int64_t tile_begin;   // first tile of the scene in the launch's numbering
     int k;
     float eps;
-    int flags;            // bit 0: eps relative to ||x||, bit 1: FP64 refit
+    int flags;            // bit 0: eps relative to ||x||, bit 1: FP64 refit, bits 8..15: d
     int cls;              // 4 * log2(E) + KMAX / 4 - 1
 };
 
@@ -96,12 +96,15 @@ void omp_multi_kernel(MultiArgs a) {
         }
         tally = OmpTally{};
     };
-    while (true) {
-        __syncthreads();   // every thread has read the previous tile number
-        if (tid == 0) tile_sh = (int64_t)atomicAdd(a.counter, 1);
-        __syncthreads();
-        const int64_t tile = tile_sh;
-        if (tile >= a.total_tiles) break;
+    if (tid == 0) tile_sh = (int64_t)atomicAdd(a.counter, 1);
+    __syncthreads();
+    int64_t tile = tile_sh;
+    while (tile < a.total_tiles) {
+        // the next tile's number is fetched while this tile is encoded; it
+        // reaches tile_sh after the tile body, whose first barrier every
+        // thread passes only after reading the current number
+        int nxt = 0;
+        if (tid == 0) nxt = atomicAdd(a.counter, 1);
         int si = 0;
         for (int q = 1; q < a.n; ++q) si += a.sc[q].tile_begin <= tile ? 1 : 0;
         if (si != cur) {
@@ -109,7 +112,8 @@ void omp_multi_kernel(MultiArgs a) {
             cur = si;
         }
         const SceneDesc &sd = a.sc[si];
-        const DictDev dict = *sd.dict;
+        DictDev dict = *sd.dict;
+        dict.d = sd.flags >> 8;   // from the kernel arguments: the tile loads need not wait for *sd.dict
         int tidv = tid;   // recomputed per tile rather than held live
         asm volatile("" : "+v"(tidv));
         const OmpParams p = scene_params(sd);
@@ -124,9 +128,12 @@ void omp_multi_kernel(MultiArgs a) {
             SC_BODY(1, 2, 4) SC_BODY(1, 2, 8) SC_BODY(1, 2, 12) SC_BODY(1, 2, 16)
             SC_BODY(2, 4, 4) SC_BODY(2, 4, 8) SC_BODY(2, 4, 12) SC_BODY(2, 4, 16)
             SC_BODY(3, 8, 4) SC_BODY(3, 8, 8) SC_BODY(3, 8, 12) SC_BODY(3, 8, 16)
-            default: break;
+            default: __syncthreads(); break;   // (classes are checked on the host) the body's barrier
         }
 #undef SC_BODY
+        if (tid == 0) tile_sh = (int64_t)nxt;
+        __syncthreads();
+        tile = tile_sh;
     }
     flush();
 }
@@ -201,7 +208,7 @@ hipError_t launch_omp_multi(const sc_scene *scenes, const int *order, int n, int
         d.tile_begin = t0;
         d.k = s.k;
         d.eps = s.eps;
-        d.flags = ((s.flags & SC_EPS_RELATIVE) ? 1 : 0) | ((s.flags & SC_NO_FP64_REFIT) ? 0 : 2);
+        d.flags = ((s.flags & SC_EPS_RELATIVE) ? 1 : 0) | ((s.flags & SC_NO_FP64_REFIT) ? 0 : 2) | (h->dev.d << 8);
         const int E = h->dev.E;
         const int ei = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : 3;
         d.cls = 4 * ei + pick_kmax(s.k) / 4 - 1;
