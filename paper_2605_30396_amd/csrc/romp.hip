@@ -291,6 +291,20 @@ __global__ __launch_bounds__(LDSD ? 64 * kRWavesL : kRThreads) void omp_restrict
                     }
                 const int es = shfl_i(ei, go ? owner : lane);
                 const int j = shfl_i(myc, go ? owner : lane);
+                // the Gram gathers of the step read row jl (j itself whenever
+                // the step is taken); up to a cap of 4 they are issued here,
+                // before the shuffles below, from an in-range row (at caps
+                // 5..8 the registers they hold early would cost a wave per SIMD)
+                constexpr bool kEarly = KMAX <= 4;
+                float gjj = 0.f;
+                vR gjc;
+                if constexpr (kEarly) {
+                    const int jl = (unsigned)j < (unsigned)dict.K ? j : 0;
+                    const float *__restrict__ Gj = G + (size_t)jl * Kp;
+                    gjj = Gj[jl];
+#pragma unroll
+                    for (int e = 0; e < kRCpl; ++e) gjc[e] = Gj[cid[e] >= 0 ? cid[e] : 0];
+                }
                 const float aj = shfl_f(myal, go ? owner : lane);
                 float wsq = 0.f;
                 float w[KMAX];
@@ -304,7 +318,7 @@ __global__ __launch_bounds__(LDSD ? 64 * kRWavesL : kRThreads) void omp_restrict
                     wsq = fmaf(w[t], w[t], wsq);
                 }
                 if (go) {
-                    const float gjj = G[(size_t)j * Kp + j];
+                    if constexpr (!kEarly) gjj = G[(size_t)j * Kp + j];
                     const float l2 = gjj - wsq;
                     if (!(l2 > 1e-9f * gjj)) {
                         go = false;
@@ -317,7 +331,12 @@ __global__ __launch_bounds__(LDSD ? 64 * kRWavesL : kRThreads) void omp_restrict
                         lmin = fminf(lmin, ell);
                         vR bn;
 #pragma unroll
-                        for (int e = 0; e < kRCpl; ++e) bn[e] = cid[e] >= 0 ? G[(size_t)j * Kp + cid[e]] : 0.f;
+                        for (int e = 0; e < kRCpl; ++e) {
+                            if constexpr (kEarly)
+                                bn[e] = cid[e] >= 0 ? gjc[e] : 0.f;
+                            else
+                                bn[e] = cid[e] >= 0 ? G[(size_t)j * Kp + cid[e]] : 0.f;
+                        }
 #pragma unroll
                         for (int t = 0; t < it; ++t) bn -= w[t] * B[t];
                         bn *= inv;
