@@ -544,7 +544,9 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             for (int t = RC + kRowBatch; t < tend; ++t) {
                 float gr[E];
                 load_row<E>(G + (size_t)readlane_i(selv, t) * Kp + lane * E, gr);
-                const float gt = bc[t];
+                // from the row only past the lane-read steps: up to step
+                // kLaneBcast the row holds this step's alpha, not gamma
+                const float gt = gamma_at(t);
 #pragma unroll
                 for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, gr[e], al[e]);
             }

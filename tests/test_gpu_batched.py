@@ -39,9 +39,10 @@ def single(h, X, k, eps, corr, rc):
 
 
 # (K, k, eps, N): every class of the launch (E = 1, 2, 4, 8; KMAX = 4..16),
-# empty and one-signal scenes, ragged tails
+# empty and one-signal scenes, ragged tails; at K = 512 the caps whose bodies
+# keep 2 Gram rows (KMAX <= 12) and none (KMAX = 16) when the row cache is on
 SCENES = [(512, 12, 1e-2, 4133), (256, 16, 0.0, 1000), (128, 4, 0.0, 37), (64, 8, 0.0, 777), (512, 4, 0.0, 0),
-          (300, 12, 0.0, 1), (200, 8, 1e-2, 2049), (90, 16, 0.0, 513)]
+          (300, 12, 0.0, 1), (200, 8, 1e-2, 2049), (90, 16, 0.0, 513), (512, 8, 0.0, 333), (512, 16, 0.0, 701)]
 
 TUNINGS = [None,
            dict(tile=32, row_cache=4, wg_per_cu=1, order=sc.ORDER_GIVEN, corr=sc.CORR_MFMA),

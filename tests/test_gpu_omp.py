@@ -106,7 +106,10 @@ MODES = [(0, sc.CORR_MFMA), (0, sc.CORR_VALU), (sc.PREC_BF16, None)]
 @pytest.mark.parametrize("flags,corr", MODES, ids=["fp32-mfma", "fp32-valu", "bf16x6"])
 @pytest.mark.parametrize("K,k,eps,s", [(512, 12, 0.0, 4), (512, 12, 1e-2, 4), (128, 16, 0.0, 8),
                                        (256, 8, 1e-2, 4), (90, 12, 0.0, 6), (1000, 8, 0.0, 4),
-                                       (640, 4, 0.0, 3), (48, 32, 0.0, 8)])
+                                       (640, 4, 0.0, 3), (48, 32, 0.0, 8),
+                                       # K > 256 with caps of 16 and more: pursuits past the
+                                       # lane-read steps with Gram rows re-read from L2
+                                       (512, 16, 1e-2, 8), (1000, 16, 1e-2, 8), (512, 24, 1e-2, 8)])
 def test_dictionary_and_sparsity_shapes(K, k, eps, s, flags, corr):
     rng = I.rng_for(1000 + K + k)
     D = I.random_dictionary(rng, K)
@@ -129,8 +132,8 @@ def test_precision_modes_on_near_duplicates(flags, corr):
     print(flags, corr, r, stats)
 
 
-@pytest.mark.parametrize("K", [256, 512])
-def test_row_cache_settings_give_the_same_codes(K):
+@pytest.mark.parametrize("K,k", [(256, 12), (512, 12), (512, 16)])
+def test_row_cache_settings_give_the_same_codes(K, k):
     """The row caches of the FP32 and split-BF16 encoders are separate
     settings; either value leaves the codes unchanged (cached Gram rows are
     the same values, summed in the same order)."""
@@ -145,7 +148,7 @@ def test_row_cache_settings_give_the_same_codes(K):
             h.set_tuning(key, rc)
             h.set_tuning(other, 4 - rc)   # the other encoder's setting must not matter
             assert h.get_tuning(key) == rc
-            out = sc.omp_encode(h, Xg, 12, 1e-3, flags)
+            out = sc.omp_encode(h, Xg, k, 1e-3, flags)
             runs.append([t.cpu().numpy() for t in out])
         np.testing.assert_array_equal(runs[0][0], runs[1][0])
         np.testing.assert_array_equal(runs[0][2], runs[1][2])
