@@ -507,7 +507,7 @@ def main():
             del Xs
         Nb = sum(sp["N"] for sp in specs)
         log(f"batched inputs ({Nb} signals) in {time.perf_counter() - tb:.1f} s")
-        tuning, tms = autotune.tune_batched(scenes, sample=65536, use_cache=False)
+        tuning, tms = autotune.tune_batched(scenes, sample=1 << 18, use_cache=False)
         outs = sc.omp_encode_batched(scenes, tuning)
         for _ in range(args.warmup):
             sc.omp_encode_batched(scenes, tuning)
