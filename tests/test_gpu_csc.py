@@ -201,6 +201,25 @@ def test_one_pass_csc_encoder_against_oracle(N):
     h.destroy()
 
 
+@pytest.mark.parametrize("K,k", [(512, 24), (1000, 16)])
+def test_one_pass_csc_encoder_long_caps_large_dictionaries(K, k):
+    """8-sparse signals over K > 256 dictionaries at eps = 1e-2 with caps of
+    16 and 24: pursuits of about eight steps, past the steps whose
+    broadcasts are lane reads, with every Gram row re-read from the cache
+    (no row cache at these shapes); columns against the oracle."""
+    rng = I.rng_for(580 + K + k)
+    D = I.random_dictionary(rng, K)
+    X, _, _ = I.sparse_signals(rng, D, 2100, 8, 1e-3)
+    h = sc.gram_precompute(torch.from_numpy(D).to(DEV))
+    colptr, rows, vals, resid = (t.cpu().numpy() for t in sc.omp_encode_csc(h, torch.from_numpy(X).to(DEV), k,
+                                                                            1e-2))
+    sep, steps = _csc_columns_against_oracle(D, X, k, 1e-2, False, colptr, rows, vals, resid)
+    print(K, k, sep.mean(), steps)
+    assert sep.mean() > 0.4 and steps > 0.6, (sep.mean(), steps)
+    assert np.diff(colptr).max() > 4   # the pursuits run past step 4
+    h.destroy()
+
+
 def test_one_pass_csc_encoder_sparse_and_refit():
     """4-sparse signals over a K = 512 dictionary at eps = 1e-2 (columns of
     about four atoms, 200 tiles), plus a support refit in FP64 inside the
