@@ -398,8 +398,9 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
     constexpr int kRowBatch = RCQ > 0 ? 1 : (KMAX >= 16 ? 2 : 3);   // within 128 VGPRs (4 waves per SIMD)
     constexpr int NL = KMAX <= 16 ? 16 : 32;                          // lanes that hold selected atoms
     // steps whose broadcasts are lane reads instead of LDS round trips (measured:
-    // faster for the wide rows of K > 256, slower for K <= 256)
-    constexpr int kLaneBcast = E >= 8 ? 4 : 0;
+    // faster for the wide rows of K > 256, slower for K <= 256; 5 steps by a
+    // hair over 4 and 6 at K = 512)
+    constexpr int kLaneBcast = E >= 8 ? 5 : 0;
     const int d = dict.d, K = dict.K;
     // k and the lane index are re-read as opaque values per signal, so the
     // per-step tests against them are made where they are used rather than
