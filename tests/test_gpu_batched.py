@@ -73,6 +73,39 @@ def test_batched_equals_single_dictionary(tuning):
         h.destroy()
 
 
+def test_thirty_two_small_scenes_in_one_launch():
+    """The most scenes a launch takes (32): 0..97 signals each over six
+    dictionaries of every class (several scenes share a handle), caps 4..16,
+    eps 0 or 1e-2; workgroups switch scenes many times and fetch each next
+    tile number while encoding the current tile.  Every scene's codes equal
+    the single-dictionary encoder's with the same correlation stage and row
+    cache, bit for bit."""
+    Ks = [64, 128, 256, 512, 90, 300]
+    hs, Ds = [], []
+    for i, K in enumerate(Ks):
+        D = I.random_dictionary(I.rng_for(700 + i), K)
+        Ds.append(D)
+        hs.append(sc.gram_precompute(torch.from_numpy(D).to(DEV)))
+    sizes = I.rng_for(710).integers(0, 98, size=32)
+    scenes, which = [], []
+    for q in range(32):
+        hi, k = q % len(Ks), (4, 8, 12, 16)[(q // len(Ks)) % 4]
+        X, _, _ = I.sparse_signals(I.rng_for(720 + q), Ds[hi], int(sizes[q]), min(4, k), 1e-3)
+        scenes.append(dict(dict=hs[hi], X=torch.from_numpy(X).to(DEV), k=k, eps=1e-2 if q % 3 == 0 else 0.0))
+        which.append(hi)
+    for t in (dict(tile=32, row_cache=4, wg_per_cu=1, order=sc.ORDER_GIVEN, corr=sc.CORR_MFMA),
+              dict(tile=16, row_cache=0, wg_per_cu=0, order=sc.ORDER_COST, corr=sc.CORR_VALU)):
+        outs = sc.omp_encode_batched(scenes, t)
+        torch.cuda.synchronize()
+        for q, s in enumerate(scenes):
+            g = to_np(outs[q])
+            ref = single(hs[which[q]], s["X"], s["k"], s["eps"], t["corr"], t["row_cache"])
+            for key in ("idx", "count", "coef", "resid"):
+                np.testing.assert_array_equal(g[key], ref[key], err_msg=f"tuning {t} scene {q} {key}")
+    for h in hs:
+        h.destroy()
+
+
 def test_sixteen_scene_batch_against_oracle():
     """The 16-scene batch (sizes log-uniform in 50k..6M, K in {128, 256, 512},
     k in {4, 8, 12, 16}, eps = 0) with each scene cut to 20,000 signals; all
