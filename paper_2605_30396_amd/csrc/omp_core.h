@@ -521,10 +521,10 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
             for (int e = 0; e < E; ++e) al[e] = fmaf(-gt, rc[t][e], al[e]);
         }
         // rows RC .. it-2 from L2: the first kRowBatch with their loads in
-        // flight together, later ones (long supports only) one at a time in
-        // a real loop, whose trip count is kept opaque to the optimiser so
-        // that it does not unroll it and hold every row at once; row it-1 is
-        // nrow
+        // flight together, later ones (long supports only) one or two at a
+        // time in a real loop, whose trip count is kept opaque to the
+        // optimiser so that it does not unroll it and hold every row at once;
+        // row it-1 is nrow
 #pragma unroll
         for (int t0 = RC; t0 < (it - 1 < RC + kRowBatch ? it - 1 : RC + kRowBatch); t0 += kRowBatch) {
             float gr[kRowBatch][E];
@@ -542,7 +542,20 @@ __device__ __forceinline__ void omp_pursuit(const DictDev &dict, const OmpParams
         }
         if (it - 1 > RC + kRowBatch) {
             const int tend = (it - 1) | (k >> 16);   // k <= 32: the value is it - 1
-            for (int t = RC + kRowBatch; t < tend; ++t) {
+            int t = RC + kRowBatch;
+            if constexpr (E <= 4) {   // rows in pairs, both loads in flight (registers to spare here)
+                for (; t + 1 < tend; t += 2) {
+                    float g0[E], g1[E];
+                    load_row<E>(G + (size_t)readlane_i(selv, t) * Kp + lane * E, g0);
+                    load_row<E>(G + (size_t)readlane_i(selv, t + 1) * Kp + lane * E, g1);
+                    const float gt0 = gamma_at(t), gt1 = gamma_at(t + 1);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) al[e] = fmaf(-gt0, g0[e], al[e]);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) al[e] = fmaf(-gt1, g1[e], al[e]);
+                }
+            }
+            for (; t < tend; ++t) {
                 float gr[E];
                 load_row<E>(G + (size_t)readlane_i(selv, t) * Kp + lane * E, gr);
                 // from the row only past the lane-read steps: up to step
